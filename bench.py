@@ -1,0 +1,275 @@
+"""Benchmark of the PW advection hot path on one MI355X.
+
+One step = one pass of the whole hot path over the 4096x4096x64 FP64 grid
+(1.07e9 cells, halo 2): forward source terms (su, sv, sw) and the gather
+adjoint (gu, gv, gw) for multipliers (lu, lv, lw), in one fused launch.
+Inputs are generated on the device by the library's counter-based generator
+and halo-filled before the timed region, so the timed region holds only the
+advection kernel.
+
+Printed: one JSON line with the headline value (FP64 fused fwd+adj Gcells/s),
+the roofline of that kernel (algorithmic bytes / measured average launch time
+against 8 TB/s HBM), per-path figures (fwd / adj / fused in FP64 and FP32),
+and the CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
+       [--kernel auto|direct|march] [--no-cpu-baseline] [--paths-reps R]
+"""
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {  # algorithmic: each input read once, each output written once
+    ("fwd", 8): 48, ("adj", 8): 72, ("fused", 8): 96,
+    ("fwd", 4): 24, ("adj", 4): 36, ("fused", 4): 48,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2010_01545_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    e = rec.get("kernels", {}).get(kernel_name)
+    if not e or e.get("workload") != workload or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+class Grid:
+    def __init__(self, pw, torch, nx, ny, nz, h, dtype, seed, with_lambda):
+        self.nx, self.ny, self.nz, self.h = nx, ny, nz, h
+        self.cells = nx * ny * nz
+        shape = (nx + 2 * h, ny + 2 * h, nz + 2 * h)
+        dev = torch.device("cuda:0")
+        mk = lambda: torch.empty(shape, dtype=dtype, device=dev)
+        self.f = [mk() for _ in range(3)]
+        for fid, t in enumerate(self.f):
+            pw.fill_uniform(t, h, seed, fid, 10.0, zero_lids=(fid == 2))
+            pw.halo_periodic(t, h)
+        self.l = []
+        if with_lambda:
+            self.l = [mk() for _ in range(3)]
+            for q, t in enumerate(self.l):
+                pw.fill_uniform(t, h, seed, 3 + q, 1.0, False)
+                pw.halo_periodic(t, h)
+        self.s = [mk() for _ in range(3)]
+        self.g = [mk() for _ in range(3)] if with_lambda else []
+        from paper_2010_01545_amd import inputs
+        tzc1, tzc2, self.tcx, self.tcy = inputs.coefficients(nz)
+        self.t1 = torch.from_numpy(tzc1).to(dev)
+        self.t2 = torch.from_numpy(tzc2).to(dev)
+
+    def launch(self, pw, path):
+        if path == "fwd":
+            pw.fwd(*self.f, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.s)
+        elif path == "adj":
+            pw.adj(*self.f, *self.l, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.g)
+        else:
+            pw.fwd_adj(*self.f, *self.l, self.t1, self.t2, self.tcx, self.tcy, self.h,
+                       out=self.s + self.g)
+
+
+def time_launches(torch, fn, reps):
+    """Per-launch durations (ms) from HIP events recorded on the stream the
+    kernels are launched on (torch's current stream)."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for r in range(reps):
+        fn()
+        ev[r + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]
+
+
+def path_record(path, esize, cells, times_ms):
+    ts = sorted(times_ms)
+    avg = sum(times_ms) / len(times_ms)
+    bpc = BYTES_PER_CELL[(path, esize)]
+    return {
+        "gcells_per_s": cells / (avg * 1e-3) / 1e9,
+        "ms_avg": avg, "ms_min": ts[0], "ms_median": ts[len(ts) // 2],
+        "alg_bytes_per_cell": bpc,
+        "alg_GBps": bpc * cells / (avg * 1e-3) / 1e9,
+        "hbm_frac": bpc * cells / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "reps": len(times_ms),
+    }
+
+
+def cpu_baseline(nx, ny, nz, seed, budget_s=12.0, planes=32):
+    """Oracle forward + scatter adjoint (single thread, FP64) on x-planes
+    0..planes-1 of the workload, repeated until budget_s of oracle time."""
+    import numpy as np
+    import oracle
+    from paper_2010_01545_amd import inputs
+    h = 2
+    tzc1, tzc2, tcx, tcy = inputs.coefficients(nz)
+
+    def slab(a):  # x halo from the true neighbour planes, y periodic, z pad 0
+        s = np.pad(a, ((0, 0), (h, h), (0, 0)), mode="wrap")
+        return np.ascontiguousarray(np.pad(s, ((0, 0), (0, 0), (h, h))))
+
+    f = [slab(a) for a in inputs.winds(seed, nx, ny, nz, x0=-h, x1=planes + h)]
+    lam = [slab(a) for a in inputs.multipliers_uniform(seed, nx, ny, nz, x0=-h, x1=planes + h)]
+    cells = planes * ny * nz
+    spent, reps = 0.0, 0
+    while spent < budget_s:
+        t0 = time.perf_counter()
+        oracle.fwd(*f, tzc1, tzc2, tcx, tcy, h)
+        oracle.adj(*f, *lam, tzc1, tzc2, tcx, tcy, h)
+        spent += time.perf_counter() - t0
+        reps += 1
+    fused = cells * reps / spent / 1e9
+    # the forward alone with the OpenMP build of the same source
+    threads = os.cpu_count() or 1
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    t0 = time.perf_counter()
+    nrep = 0
+    while time.perf_counter() - t0 < 2.0:
+        oracle.fwd(*f, tzc1, tzc2, tcx, tcy, h, threaded=True)
+        nrep += 1
+    fwd_omp = cells * nrep / (time.perf_counter() - t0) / 1e9
+    return {
+        "value": fused, "unit": "Gcells/s", "cores": 1, "kind": "oracle",
+        "sample": "oracle fwd + scatter adjoint, FP64, single thread, on x-planes 0..%d of the "
+                  "%dx%dx%d grid (%d cells) repeated %d times (%.1f s)"
+                  % (planes - 1, nx, ny, nz, cells, reps, spent),
+        "fwd_openmp": {"value": fwd_omp, "unit": "Gcells/s", "threads": threads,
+                       "sample": "oracle forward, OpenMP build, same slab"},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper_scale")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "direct", "march"])
+    ap.add_argument("--paths-reps", type=int, default=10)
+    ap.add_argument("--no-paths", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the PW advection path is measured on one "
+              "GPU's grid; a multi-GPU run (x-slab decomposition with halo exchange) is not "
+              "part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_01545_amd import inputs, pwadvect as pw
+
+    wl = inputs.WORKLOADS[args.workload]
+    nx, ny, nz, seed = wl["nx"], wl["ny"], wl["nz"], wl["seed"]
+    h = inputs.HALO
+    cells = nx * ny * nz
+    pw.set_kernel(args.kernel)
+    torch.cuda.init()
+    log("bench: %s %dx%dx%d, kernel=%s" % (args.workload, nx, ny, nz, args.kernel))
+
+    if args.only:
+        path, dt = args.only.split(":")
+        g = Grid(pw, torch, nx, ny, nz, h, torch.float64 if dt == "f64" else torch.float32, seed,
+                 path != "fwd")
+        torch.cuda.synchronize()
+        for _ in range(args.warmup + args.steps):
+            g.launch(pw, path)
+        torch.cuda.synchronize()
+        log("bench: profile run of %s done" % args.only)
+        return
+
+    # ---- headline: FP64 fused forward + adjoint
+    g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True)
+    torch.cuda.synchronize()
+    log("bench: inputs ready")
+    for _ in range(args.warmup):
+        g.launch(pw, "fused")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times = time_launches(torch, lambda: g.launch(pw, "fused"), args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    head = path_record("fused", 8, cells, times)
+    log("bench: fused f64 %.2f ms/launch, %.1f Gcells/s" % (head["ms_avg"], head["gcells_per_s"]))
+
+    paths = {"fused_f64": head}
+    if not args.no_paths:
+        for p in ("fwd", "adj"):
+            g.launch(pw, p)
+            paths[p + "_f64"] = path_record(p, 8, cells, time_launches(torch, lambda: g.launch(pw, p),
+                                                                       args.paths_reps))
+            log("bench: %s f64 %.2f ms" % (p, paths[p + "_f64"]["ms_avg"]))
+    del g
+    torch.cuda.empty_cache()
+    if not args.no_paths:
+        g = Grid(pw, torch, nx, ny, nz, h, torch.float32, seed, True)
+        for p in ("fwd", "adj", "fused"):
+            g.launch(pw, p)
+            paths[p + "_f32"] = path_record(p, 4, cells, time_launches(torch, lambda: g.launch(pw, p),
+                                                                       args.paths_reps))
+            log("bench: %s f32 %.2f ms" % (p, paths[p + "_f32"]["ms_avg"]))
+        del g
+        torch.cuda.empty_cache()
+        for p in ("fwd", "fused"):
+            paths[p + "_f32"]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + "_f32"]["ms_avg"]
+
+    kname = "fused_f64"
+    traffic = measured_traffic(kname, args.workload)
+    achieved = head["alg_GBps"]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "pw_advect_fwd_adj FP64 (%s)" % pw.get_kernel(),
+                "alg_bytes_per_launch": 96 * cells}
+
+    out = {
+        "metric": "Gcells/s PW advection fwd & fwd+adj, FP64 vs FP32, % of HBM roofline",
+        "value": head["gcells_per_s"], "unit": "Gcells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (counter-based U(-10,10) winds, U(-1,1) multipliers)",
+        "config": {"workload": "%s %dx%dx%d halo %d, FP64 fused forward + adjoint"
+                   % (args.workload, nx, ny, nz, h), "nx": nx, "ny": ny, "nz": nz, "halo": h,
+                   "cells": cells, "kernel": args.kernel},
+        "roofline": roofline,
+        "paths": paths,
+        "source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(nx, ny, nz, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

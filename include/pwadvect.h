@@ -1,0 +1,173 @@
+/*
+ * pwadvect.h -- C ABI of libpwadvect, the MI355X (gfx950) implementation of
+ * the Piacsek-Williams (PW) momentum-advection source terms of the MONC
+ * model, as ported in N. Brown, "Exploring the acceleration of the Met Office
+ * NERC Cloud model using FPGAs" (section 2.1, Listing 1; section 3, Listing 2
+ * gives the kernel's external interface: six field arrays plus the grid
+ * sizes as scalars).
+ *
+ * ---------------------------------------------------------------- layout
+ * Every field array (u, v, w, the multipliers lu, lv, lw, and the outputs
+ * su, sv, sw, gu, gv, gw) is a C-contiguous "storage" array of
+ *     (nx + 2*halo) x (ny + 2*halo) x (nz + 2*halo)
+ * elements, z fastest, then y, then x: the Fortran F(k, j, i) layout of the
+ * paper (section 2.1), in which one column and then consecutive y-columns are
+ * contiguous (section 3, Listings 3 and 4).  Interior cell (i, j, k) with
+ * 0 <= i < nx, 0 <= j < ny, 0 <= k < nz is element
+ *     ((i + halo) * (ny + 2*halo) + (j + halo)) * (nz + 2*halo) + (k + halo).
+ * Element type: double for PW_F64, float for PW_F32.
+ * tzc1, tzc2 are double arrays of length nz indexed by interior level k, for
+ * both element types (the FP32 path rounds them to float where it uses them).
+ * tcx, tcy are passed by value as double (rounded to float by PW_F32).
+ *
+ * Every pointer is a device pointer (hipMalloc / torch device memory) owned by
+ * the caller.  The library allocates no device memory, keeps no state between
+ * calls other than the kernel selection and the last error text, and is
+ * thread-safe apart from pw_set_kernel.
+ *
+ * ---------------------------------------------------------------- semantics
+ * Levels follow Listing 1: Fortran k = 2..z_size is interior k = 1..nz-1.
+ *   su, sv: computed on levels 1..nz-1; the top level nz-1 keeps only the
+ *           tzc1 term; level 0 is 0.
+ *   sw:     computed on levels 1..nz-2; levels 0 and nz-1 are 0.
+ * su follows Listing 1.  The paper omits sv and sw ("very similar"); this
+ * library computes sv as the x<->y transpose of su and sw as the same
+ * upwind-value-times-face-sum scheme staggered in z with tzc1/tzc2.
+ * Outputs are ASSIGNED (Listing 1 assigns su), never accumulated.
+ * Only interior columns of outputs are written: their interior levels get the
+ * result and their 2*halo z-halo levels get 0.  x/y halo columns of outputs are
+ * never written.
+ * Inputs must have their x/y halos filled (periodic: pw_halo_periodic or
+ * pw_pad_periodic).  z-halo levels of inputs are never used; they may hold any
+ * value, including NaN.
+ *
+ * All calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ * stream) and return as soon as the work is queued.
+ *
+ * ---------------------------------------------------------------- errors
+ * Each call returns PW_OK or a negative code and, for a negative code, sets a
+ * thread-local message readable with pw_last_error().  Argument checks happen
+ * before any GPU work is queued; nothing is written on error.
+ *   PW_ERR_ARG          null pointer, nx < 1, ny < 1, nz < 2, halo < 1,
+ *                       unknown dtype, not a device pointer, or an array that
+ *                       does not fit inside its device allocation
+ *   PW_ERR_ALIAS        an output overlaps an input or another output
+ *   PW_ERR_ALIGN        a pointer is not aligned to its element type
+ *   PW_ERR_SIZE         n + 2*halo overflows int, or a storage byte count
+ *                       overflows int64
+ *   PW_ERR_UNSUPPORTED  the selected kernel cannot run this shape
+ *   PW_ERR_HIP          the HIP runtime reported an error at launch
+ */
+#ifndef PWADVECT_H
+#define PWADVECT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { PW_F64 = 0, PW_F32 = 1 } pw_dtype;
+
+enum {
+    PW_OK = 0,
+    PW_ERR_ARG = -1,
+    PW_ERR_ALIAS = -2,
+    PW_ERR_ALIGN = -3,
+    PW_ERR_SIZE = -4,
+    PW_ERR_UNSUPPORTED = -5,
+    PW_ERR_HIP = -6
+};
+
+/* Kernel selection (process-wide; see pw_set_kernel). */
+enum {
+    PW_KERNEL_AUTO = 0,   /* x-marching kernel where it applies, else direct */
+    PW_KERNEL_DIRECT = 1, /* one thread per storage level, any nz >= 2 */
+    PW_KERNEL_MARCH = 2   /* x-marching, LDS-staged kernel; nz == 64 only */
+};
+
+/*
+ * Forward source terms (section 2.1, Listing 1; section 3, Listing 2).
+ * Reads u, v, w (storage arrays with filled x/y halos) and writes su, sv, sw.
+ */
+int pw_advect_fwd(const void *u, const void *v, const void *w,
+                  const double *tzc1, const double *tzc2, double tcx, double tcy,
+                  int nx, int ny, int nz, int halo,
+                  void *su, void *sv, void *sw, int dtype, void *stream);
+
+/*
+ * Adjoint (vector-Jacobian product) of pw_advect_fwd, gather form.
+ * For L = sum over interior cells of lu*su + lv*sv + lw*sw, writes into the
+ * interior of gu, gv, gw the gradient of L with respect to the interior values
+ * of u, v, w of the x/y-periodic problem (halos being copies of interior
+ * cells).  u, v, w, lu, lv, lw must all have periodic x/y halos filled.  The
+ * fields are read again, not stored from the forward; no atomics are used, so
+ * the result is bitwise reproducible.  Multipliers on levels whose source
+ * term is identically 0 (level 0; level nz-1 of sw) have no effect.
+ */
+int pw_advect_adj(const void *u, const void *v, const void *w,
+                  const void *lu, const void *lv, const void *lw,
+                  const double *tzc1, const double *tzc2, double tcx, double tcy,
+                  int nx, int ny, int nz, int halo,
+                  void *gu, void *gv, void *gw, int dtype, void *stream);
+
+/*
+ * pw_advect_fwd and pw_advect_adj in one pass over the inputs: writes
+ * su, sv, sw and gu, gv, gw with the values the two separate calls give.
+ */
+int pw_advect_fwd_adj(const void *u, const void *v, const void *w,
+                      const void *lu, const void *lv, const void *lw,
+                      const double *tzc1, const double *tzc2, double tcx, double tcy,
+                      int nx, int ny, int nz, int halo,
+                      void *su, void *sv, void *sw, void *gu, void *gv, void *gw,
+                      int dtype, void *stream);
+
+/*
+ * Periodic halo fill in place (the halo swap that precedes advection in each
+ * timestep, section 2.1, for a domain that is periodic in x and y): copies
+ * whole storage columns so that storage column (i, j) for i or j outside the
+ * interior equals interior column (i mod nx, j mod ny), z-halo levels
+ * included.  Interior columns are not written.
+ */
+int pw_halo_periodic(void *storage, int nx, int ny, int nz, int halo, int dtype, void *stream);
+
+/*
+ * Builds a storage array from a compact interior array (nx, ny, nz) (C order,
+ * same element type): interior columns get the interior values and 0 in their
+ * z-halo levels, halo columns get their periodic images.  `interior` and
+ * `storage` must not overlap.
+ */
+int pw_pad_periodic(const void *interior, void *storage, int nx, int ny, int nz, int halo,
+                    int dtype, void *stream);
+
+/*
+ * Input generator (not part of the scheme): writes interior columns of a
+ * storage array with amp * t, where t in [-1, 1) is the SplitMix64
+ * counter-based uniform of Steele, Lea and Flood (OOPSLA 2014) for seed
+ * `seed`, stream `field_id` and counter = interior linear index
+ * (i*ny + j)*nz + k:  z = mix(seed*256 + field_id + (counter+1)*0x9E3779B97F4A7C15),
+ * t = ((z >> 11) - 2^52) * 2^-52, value = amp * t rounded once (to double,
+ * then to float for PW_F32).  With zero_lids != 0 levels 0 and nz-1 are 0.
+ * z-halo levels are set to 0; x/y halo columns are not written.
+ */
+int pw_fill_uniform(void *storage, int nx, int ny, int nz, int halo,
+                    unsigned long long seed, int field_id, double amp, int zero_lids,
+                    int dtype, void *stream);
+
+/*
+ * Selects the kernel family used by the three advection calls, for every
+ * thread of the process (set it before concurrent use).  Returns the
+ * previous selection, or PW_ERR_ARG for an unknown value.
+ */
+int pw_set_kernel(int kernel);
+int pw_get_kernel(void);
+
+/* Message for the last non-zero return on the calling thread ("" if none). */
+const char *pw_last_error(void);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int pw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWADVECT_H */

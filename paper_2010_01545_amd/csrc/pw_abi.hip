@@ -1,0 +1,340 @@
+// pw_abi.hip -- the extern "C" entry points of libpwadvect: argument
+// validation (all of it before any work is queued), kernel selection and
+// launch-error reporting.  See include/pwadvect.h for the contract.
+#include <atomic>
+#include <climits>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/pwadvect.h"
+#include "pw_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+std::atomic<int> g_kernel{PW_KERNEL_AUTO};
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ok()
+{
+    g_err[0] = '\0';
+    return PW_OK;
+}
+
+size_t elem_size(int dtype) { return dtype == PW_F64 ? 8 : 4; }
+
+// Shape checks shared by every entry point; fills g and the byte count of
+// one storage array.
+int check_shape(int nx, int ny, int nz, int halo, int dtype, Geom& g, size_t& bytes)
+{
+    if (dtype != PW_F64 && dtype != PW_F32) return fail(PW_ERR_ARG, "unknown dtype %d", dtype);
+    if (nx < 1 || ny < 1) return fail(PW_ERR_ARG, "nx=%d, ny=%d: need nx >= 1 and ny >= 1", nx, ny);
+    if (nz < 2) return fail(PW_ERR_ARG, "nz=%d: need nz >= 2", nz);
+    if (halo < 1) return fail(PW_ERR_ARG, "halo=%d: need halo >= 1", halo);
+    const long long Sx = (long long)nx + 2LL * halo;
+    const long long Sy = (long long)ny + 2LL * halo;
+    const long long Sz = (long long)nz + 2LL * halo;
+    if (Sx > INT_MAX || Sy > INT_MAX || Sz > INT_MAX)
+        return fail(PW_ERR_SIZE, "n + 2*halo overflows int");
+    // per-plane thread index of the kernels is a 32-bit int
+    if (Sy * Sz > (long long)INT_MAX - 1024)
+        return fail(PW_ERR_SIZE, "(ny+2h)*(nz+2h) = %lld exceeds the per-plane limit", Sy * Sz);
+    const long long es = (long long)elem_size(dtype);
+    if (Sx > LLONG_MAX / Sy || Sx * Sy > LLONG_MAX / Sz || Sx * Sy * Sz > LLONG_MAX / es)
+        return fail(PW_ERR_SIZE, "storage byte count overflows int64");
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.h = halo;
+    g.Sx = (int)Sx;
+    g.Sy = (int)Sy;
+    g.Sz = (int)Sz;
+    g.sy = (int)Sz;
+    g.sx = Sy * Sz;
+    bytes = (size_t)(Sx * Sy * Sz * es);
+    return PW_OK;
+}
+
+struct Arr {
+    const void* p;
+    size_t bytes;
+    size_t align;
+    const char* name;
+};
+
+int check_host_side(const Arr* in, int nin, const Arr* out, int nout)
+{
+    for (int q = 0; q < nin + nout; q++) {
+        const Arr& a = q < nin ? in[q] : out[q - nin];
+        if (!a.p) return fail(PW_ERR_ARG, "%s is NULL", a.name);
+        if ((uintptr_t)a.p % a.align) return fail(PW_ERR_ALIGN, "%s is not %zu-byte aligned", a.name, a.align);
+    }
+    for (int o = 0; o < nout; o++) {
+        const uintptr_t ob = (uintptr_t)out[o].p, oe = ob + out[o].bytes;
+        for (int q = 0; q < nin + nout; q++) {
+            if (q == nin + o) continue;
+            const Arr& a = q < nin ? in[q] : out[q - nin];
+            const uintptr_t ab = (uintptr_t)a.p, ae = ab + a.bytes;
+            if (ob < ae && ab < oe)
+                return fail(PW_ERR_ALIAS, "output %s overlaps %s", out[o].name, a.name);
+        }
+    }
+    return PW_OK;
+}
+
+// Device-pointer and allocation-extent checks (host queries, no GPU work).
+int check_device(const Arr* arrs, int n)
+{
+    for (int q = 0; q < n; q++) {
+        const Arr& a = arrs[q];
+        hipPointerAttribute_t attr;
+        std::memset(&attr, 0, sizeof attr);
+        if (hipPointerGetAttributes(&attr, a.p) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PW_ERR_ARG, "%s is not a device pointer", a.name);
+        }
+        if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+            return fail(PW_ERR_ARG, "%s is not device memory", a.name);
+        hipDeviceptr_t base = nullptr;
+        size_t size = 0;
+        if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)a.p) == hipSuccess && size > 0) {
+            const uintptr_t b = (uintptr_t)base, p = (uintptr_t)a.p;
+            if (p < b || p + a.bytes > b + size)
+                return fail(PW_ERR_ARG, "%s (%zu bytes) does not fit inside its device allocation",
+                            a.name, a.bytes);
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    return PW_OK;
+}
+
+int launched(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+// Resolve the kernel family for a shape; -1 if the selection cannot run it.
+template <typename T>
+int resolve_kernel(const Geom& g, const Arr* arrs, int n)
+{
+    const int sel = g_kernel.load();
+    if (sel == PW_KERNEL_DIRECT) return PW_KERNEL_DIRECT;
+    bool march = march_supported<T>(g);
+    for (int q = 0; q < n && march; q++)
+        if ((uintptr_t)arrs[q].p % 16) march = false;
+    if (sel == PW_KERNEL_MARCH) return march ? PW_KERNEL_MARCH : -1;
+    return march ? PW_KERNEL_MARCH : PW_KERNEL_DIRECT;
+}
+
+template <typename T>
+int do_fwd(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
+           double tcx, double tcy, const Geom& g, size_t bytes, void* su, void* sv, void* sw,
+           hipStream_t stream)
+{
+    const Arr in[5] = {{u, bytes, sizeof(T), "u"}, {v, bytes, sizeof(T), "v"}, {w, bytes, sizeof(T), "w"},
+                       {tzc1, (size_t)g.nz * 8, 8, "tzc1"}, {tzc2, (size_t)g.nz * 8, 8, "tzc2"}};
+    const Arr out[3] = {{su, bytes, sizeof(T), "su"}, {sv, bytes, sizeof(T), "sv"}, {sw, bytes, sizeof(T), "sw"}};
+    int rc = check_host_side(in, 5, out, 3);
+    if (rc) return rc;
+    const Arr all[8] = {in[0], in[1], in[2], in[3], in[4], out[0], out[1], out[2]};
+    rc = check_device(all, 8);
+    if (rc) return rc;
+    const Arr fields[6] = {in[0], in[1], in[2], out[0], out[1], out[2]};
+    const int kern = resolve_kernel<T>(g, fields, 6);
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64 and 16-byte aligned arrays");
+    FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, (T)tcx, (T)tcy, (T*)su, (T*)sv, (T*)sw};
+    (void)hipGetLastError();
+    if (kern == PW_KERNEL_MARCH)
+        launch_fwd_march<T>(a, g, stream);
+    else
+        launch_fwd_direct<T>(a, g, stream);
+    return launched("pw_advect_fwd");
+}
+
+template <typename T>
+int do_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv, const void* lw,
+           const double* tzc1, const double* tzc2, double tcx, double tcy, const Geom& g, size_t bytes,
+           void* su, void* sv, void* sw, void* gu, void* gv, void* gw, hipStream_t stream)
+{
+    const size_t es = sizeof(T);
+    const Arr in[8] = {{u, bytes, es, "u"},   {v, bytes, es, "v"},   {w, bytes, es, "w"},
+                       {lu, bytes, es, "lu"}, {lv, bytes, es, "lv"}, {lw, bytes, es, "lw"},
+                       {tzc1, (size_t)g.nz * 8, 8, "tzc1"}, {tzc2, (size_t)g.nz * 8, 8, "tzc2"}};
+    const bool fused = su != nullptr || sv != nullptr || sw != nullptr;
+    Arr out[6];
+    int nout = 0;
+    if (fused) {
+        out[nout++] = {su, bytes, es, "su"};
+        out[nout++] = {sv, bytes, es, "sv"};
+        out[nout++] = {sw, bytes, es, "sw"};
+    }
+    out[nout++] = {gu, bytes, es, "gu"};
+    out[nout++] = {gv, bytes, es, "gv"};
+    out[nout++] = {gw, bytes, es, "gw"};
+    int rc = check_host_side(in, 8, out, nout);
+    if (rc) return rc;
+    Arr all[14];
+    int n = 0;
+    for (int q = 0; q < 8; q++) all[n++] = in[q];
+    for (int q = 0; q < nout; q++) all[n++] = out[q];
+    rc = check_device(all, n);
+    if (rc) return rc;
+    Arr fields[12];
+    int nf = 0;
+    for (int q = 0; q < 6; q++) fields[nf++] = in[q];
+    for (int q = 0; q < nout; q++) fields[nf++] = out[q];
+    const int kern = resolve_kernel<T>(g, fields, nf);
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64 and 16-byte aligned arrays");
+    AdjArgs<T> a{(const T*)u, (const T*)v, (const T*)w, (const T*)lu, (const T*)lv, (const T*)lw,
+                 tzc1, tzc2, (T)tcx, (T)tcy, (T*)su, (T*)sv, (T*)sw, (T*)gu, (T*)gv, (T*)gw};
+    (void)hipGetLastError();
+    if (kern == PW_KERNEL_MARCH)
+        launch_adj_march<T>(a, g, stream);
+    else
+        launch_adj_direct<T>(a, g, stream);
+    return launched(fused ? "pw_advect_fwd_adj" : "pw_advect_adj");
+}
+
+int check_one(const void* p, size_t bytes, size_t align, const char* name)
+{
+    const Arr a[1] = {{p, bytes, align, name}};
+    int rc = check_host_side(a, 1, nullptr, 0);
+    if (rc) return rc;
+    return check_device(a, 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pw_advect_fwd(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
+                  double tcx, double tcy, int nx, int ny, int nz, int halo, void* su, void* sv, void* sw,
+                  int dtype, void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    if (dtype == PW_F64)
+        return do_fwd<double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+    return do_fwd<float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+}
+
+int pw_advect_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
+                  const void* lw, const double* tzc1, const double* tzc2, double tcx, double tcy, int nx,
+                  int ny, int nz, int halo, void* gu, void* gv, void* gw, int dtype, void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    if (!gu || !gv || !gw) return fail(PW_ERR_ARG, "gu, gv, gw must not be NULL");
+    if (dtype == PW_F64)
+        return do_adj<double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr,
+                              nullptr, gu, gv, gw, (hipStream_t)stream);
+    return do_adj<float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr, nullptr,
+                         gu, gv, gw, (hipStream_t)stream);
+}
+
+int pw_advect_fwd_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
+                      const void* lw, const double* tzc1, const double* tzc2, double tcx, double tcy,
+                      int nx, int ny, int nz, int halo, void* su, void* sv, void* sw, void* gu, void* gv,
+                      void* gw, int dtype, void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    if (!su || !sv || !sw) return fail(PW_ERR_ARG, "su, sv, sw must not be NULL");
+    if (!gu || !gv || !gw) return fail(PW_ERR_ARG, "gu, gv, gw must not be NULL");
+    if (dtype == PW_F64)
+        return do_adj<double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv, gw,
+                              (hipStream_t)stream);
+    return do_adj<float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv, gw,
+                         (hipStream_t)stream);
+}
+
+int pw_halo_periodic(void* storage, int nx, int ny, int nz, int halo, int dtype, void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    rc = check_one(storage, bytes, elem_size(dtype), "storage");
+    if (rc) return rc;
+    (void)hipGetLastError();
+    if (dtype == PW_F64)
+        launch_halo_periodic<double>((double*)storage, g, (hipStream_t)stream);
+    else
+        launch_halo_periodic<float>((float*)storage, g, (hipStream_t)stream);
+    return launched("pw_halo_periodic");
+}
+
+int pw_pad_periodic(const void* interior, void* storage, int nx, int ny, int nz, int halo, int dtype,
+                    void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    const size_t es = elem_size(dtype);
+    const Arr in[1] = {{interior, (size_t)nx * (size_t)ny * (size_t)nz * es, es, "interior"}};
+    const Arr out[1] = {{storage, bytes, es, "storage"}};
+    rc = check_host_side(in, 1, out, 1);
+    if (rc) return rc;
+    const Arr all[2] = {in[0], out[0]};
+    rc = check_device(all, 2);
+    if (rc) return rc;
+    (void)hipGetLastError();
+    if (dtype == PW_F64)
+        launch_pad_periodic<double>((const double*)interior, (double*)storage, g, (hipStream_t)stream);
+    else
+        launch_pad_periodic<float>((const float*)interior, (float*)storage, g, (hipStream_t)stream);
+    return launched("pw_pad_periodic");
+}
+
+int pw_fill_uniform(void* storage, int nx, int ny, int nz, int halo, unsigned long long seed, int field_id,
+                    double amp, int zero_lids, int dtype, void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    if (field_id < 0 || field_id > 255) return fail(PW_ERR_ARG, "field_id=%d outside 0..255", field_id);
+    rc = check_one(storage, bytes, elem_size(dtype), "storage");
+    if (rc) return rc;
+    (void)hipGetLastError();
+    if (dtype == PW_F64)
+        launch_fill_uniform<double>((double*)storage, g, seed, field_id, amp, zero_lids, (hipStream_t)stream);
+    else
+        launch_fill_uniform<float>((float*)storage, g, seed, field_id, amp, zero_lids, (hipStream_t)stream);
+    return launched("pw_fill_uniform");
+}
+
+int pw_set_kernel(int kernel)
+{
+    if (kernel != PW_KERNEL_AUTO && kernel != PW_KERNEL_DIRECT && kernel != PW_KERNEL_MARCH)
+        return fail(PW_ERR_ARG, "unknown kernel selection %d", kernel);
+    return g_kernel.exchange(kernel);
+}
+
+int pw_get_kernel(void) { return g_kernel.load(); }
+
+const char* pw_last_error(void) { return g_err; }
+
+int pw_version(void) { return 100; }
+
+}  // extern "C"

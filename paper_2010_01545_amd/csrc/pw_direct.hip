@@ -1,0 +1,142 @@
+// pw_direct.hip -- the plain GPU form of the PW advection scheme: one thread
+// per storage level of every interior column, all operands loaded straight
+// from global memory (neighbour reuse is left to the L1/L2 caches).  It runs
+// any nz >= 2 and halo >= 1 and is the fallback of the x-marching kernels.
+//
+// Grid: blockIdx.y walks x-planes (grid-stride), blockIdx.x * 256 + tid walks
+// the ny * Sz storage levels of the plane's interior columns, z fastest, so a
+// wavefront reads and writes contiguous runs of a column.  z-halo levels of
+// interior columns are written with 0.
+#include "pw_internal.h"
+#include "pw_stencil.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Star of field f around storage element b; DIAG selects the field's two
+// diagonal neighbours (0: u, 1: v, 2: w; see pw_stencil.h).
+template <typename T, int DIAG>
+__device__ __forceinline__ Star<T> load_star(const T* __restrict__ f, long long b, long long sx, int sy)
+{
+    Star<T> s;
+    s.c = f[b];
+    s.xm = f[b - sx];
+    s.xp = f[b + sx];
+    s.ym = f[b - sy];
+    s.yp = f[b + sy];
+    s.zm = f[b - 1];
+    s.zp = f[b + 1];
+    if (DIAG == 0) {
+        s.d1 = f[b - sx + sy];
+        s.d2 = f[b - sx + 1];
+    } else if (DIAG == 1) {
+        s.d1 = f[b + sx - sy];
+        s.d2 = f[b - sy + 1];
+    } else {
+        s.d1 = f[b + sx - 1];
+        s.d2 = f[b + sy - 1];
+    }
+    return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.ny * g.Sz) return;
+    const int j = t / g.Sz;
+    const int kk = t - j * g.Sz;
+    const int k = kk - g.h;
+    for (int i = blockIdx.y; i < g.nx; i += gridDim.y) {
+        const long long b = (long long)(i + g.h) * g.sx + (long long)(j + g.h) * g.sy + kk;
+        if (k < 0 || k >= g.nz) {
+            a.su[b] = T(0);
+            a.sv[b] = T(0);
+            a.sw[b] = T(0);
+            continue;
+        }
+        const Star<T> u = load_star<T, 0>(a.u, b, g.sx, g.sy);
+        const Star<T> v = load_star<T, 1>(a.v, b, g.sx, g.sy);
+        const Star<T> w = load_star<T, 2>(a.w, b, g.sx, g.sy);
+        const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, k, g.nz);
+        T su, sv, sw;
+        pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
+        a.su[b] = su;
+        a.sv[b] = sv;
+        a.sw[b] = sw;
+    }
+}
+
+template <typename T, bool FUSED>
+__global__ void __launch_bounds__(kBlock) adj_direct_kernel(AdjArgs<T> a, Geom g)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.ny * g.Sz) return;
+    const int j = t / g.Sz;
+    const int kk = t - j * g.Sz;
+    const int k = kk - g.h;
+    for (int i = blockIdx.y; i < g.nx; i += gridDim.y) {
+        const long long b = (long long)(i + g.h) * g.sx + (long long)(j + g.h) * g.sy + kk;
+        if (k < 0 || k >= g.nz) {
+            if (FUSED) {
+                a.su[b] = T(0);
+                a.sv[b] = T(0);
+                a.sw[b] = T(0);
+            }
+            a.gu[b] = T(0);
+            a.gv[b] = T(0);
+            a.gw[b] = T(0);
+            continue;
+        }
+        const Star<T> u = load_star<T, 0>(a.u, b, g.sx, g.sy);
+        const Star<T> v = load_star<T, 1>(a.v, b, g.sx, g.sy);
+        const Star<T> w = load_star<T, 2>(a.w, b, g.sx, g.sy);
+        const Star<T> lu = load_star<T, 0>(a.lu, b, g.sx, g.sy);
+        const Star<T> lv = load_star<T, 1>(a.lv, b, g.sx, g.sy);
+        const Star<T> lw = load_star<T, 2>(a.lw, b, g.sx, g.sy);
+        const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, k, g.nz);
+        if (FUSED) {
+            T su, sv, sw;
+            pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
+            a.su[b] = su;
+            a.sv[b] = sv;
+            a.sw[b] = sw;
+        }
+        T gu, gv, gw;
+        pw_adj_cell(u, v, w, lu, lv, lw, cf, k, g.nz, gu, gv, gw);
+        a.gu[b] = gu;
+        a.gv[b] = gv;
+        a.gw[b] = gw;
+    }
+}
+
+inline dim3 direct_grid(const Geom& g)
+{
+    const int per_plane = g.ny * g.Sz;
+    const unsigned bx = (unsigned)((per_plane + kBlock - 1) / kBlock);
+    const unsigned by = (unsigned)(g.nx < 65535 ? g.nx : 65535);
+    return dim3(bx, by, 1);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
+{
+    hipLaunchKernelGGL(fwd_direct_kernel<T>, direct_grid(g), dim3(kBlock), 0, s, a, g);
+}
+
+template <typename T>
+void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
+{
+    if (a.su)
+        hipLaunchKernelGGL((adj_direct_kernel<T, true>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+    else
+        hipLaunchKernelGGL((adj_direct_kernel<T, false>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+}
+
+template void launch_fwd_direct<double>(const FwdArgs<double>&, const Geom&, hipStream_t);
+template void launch_fwd_direct<float>(const FwdArgs<float>&, const Geom&, hipStream_t);
+template void launch_adj_direct<double>(const AdjArgs<double>&, const Geom&, hipStream_t);
+template void launch_adj_direct<float>(const AdjArgs<float>&, const Geom&, hipStream_t);

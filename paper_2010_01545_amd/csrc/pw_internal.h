@@ -1,0 +1,47 @@
+// pw_internal.h -- declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+// Geometry of one storage array: interior (nx, ny, nz), halo h, strides in
+// elements of the x planes (sx) and y columns (sy = Sz).
+struct Geom {
+    int nx, ny, nz, h;
+    int Sx, Sy, Sz;   // storage extents
+    long long sx;     // Sy * Sz
+    int sy;           // Sz
+};
+
+// Operand bundles passed to the kernel launchers.
+template <typename T>
+struct FwdArgs {
+    const T *u, *v, *w;
+    const double *tzc1, *tzc2;
+    T tcx, tcy;
+    T *su, *sv, *sw;
+};
+
+template <typename T>
+struct AdjArgs {
+    const T *u, *v, *w, *lu, *lv, *lw;
+    const double *tzc1, *tzc2;
+    T tcx, tcy;
+    T *su, *sv, *sw;   // forward outputs (fused launch only; null otherwise)
+    T *gu, *gv, *gw;
+};
+
+// Direct kernels: one thread per storage level of each interior column,
+// every operand read from global memory.  Any nz >= 2, any halo >= 1.
+template <typename T> void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T> void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
+
+// x-marching kernels (nz == 64, 16-byte aligned arrays).
+template <typename T> bool march_supported(const Geom& g);
+template <typename T> void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T> void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
+
+// Utilities.
+template <typename T> void launch_halo_periodic(T* st, const Geom& g, hipStream_t s);
+template <typename T> void launch_pad_periodic(const T* in, T* st, const Geom& g, hipStream_t s);
+template <typename T> void launch_fill_uniform(T* st, const Geom& g, unsigned long long seed,
+                                               int field_id, double amp, int zero_lids,
+                                               hipStream_t s);

@@ -1,0 +1,183 @@
+"""ctypes binding of libpwadvect (argument marshalling only).
+
+Each function takes torch tensors on a ROCm device, checks that they are
+contiguous and of one storage shape, and passes raw pointers, sizes and the
+current torch stream to the C entry point of the same name in
+``include/pwadvect.h``.  All computation happens in the HIP library; if it is
+not built, importing this module raises ImportError.
+
+Storage tensors have shape (nx+2h, ny+2h, nz+2h), z fastest; the grid size is
+taken from the shape and the ``halo`` argument.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwadvect.so")
+
+PW_F64, PW_F32 = 0, 1
+KERNELS = {"auto": 0, "direct": 1, "march": 2}
+ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
+          -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpwadvect.so is not built (%s); run __graft_entry__.build() "
+                      "or python paper_2010_01545_amd/build.py" % LIB_PATH)
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+lib.pw_advect_fwd.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _vp]
+lib.pw_advect_adj.argtypes = [_vp] * 8 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _vp]
+lib.pw_advect_fwd_adj.argtypes = [_vp] * 8 + [_d, _d] + [_i] * 4 + [_vp] * 6 + [_i, _vp]
+lib.pw_halo_periodic.argtypes = [_vp] + [_i] * 5 + [_vp]
+lib.pw_pad_periodic.argtypes = [_vp, _vp] + [_i] * 5 + [_vp]
+lib.pw_fill_uniform.argtypes = [_vp] + [_i] * 4 + [ctypes.c_ulonglong, _i, _d, _i, _i, _vp]
+lib.pw_set_kernel.argtypes = [_i]
+lib.pw_last_error.restype = ctypes.c_char_p
+for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_halo_periodic",
+           "pw_pad_periodic", "pw_fill_uniform", "pw_set_kernel", "pw_get_kernel", "pw_version"):
+    getattr(lib, _f).restype = ctypes.c_int
+
+
+class PWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise PWError(rc, lib.pw_last_error().decode())
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float64:
+        return PW_F64
+    if t.dtype == torch.float32:
+        return PW_F32
+    raise TypeError("field tensors must be float64 or float32, got %s" % t.dtype)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _grid(t, halo):
+    if t.dim() != 3:
+        raise ValueError("storage tensors are 3-D (x, y, z)")
+    return tuple(int(s) - 2 * halo for s in t.shape)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _fields(ref, *ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("tensors must be on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        if t.shape != ref.shape or t.dtype != ref.dtype:
+            raise ValueError("all field tensors need one shape and dtype")
+
+
+def _profile(t, nz, device):
+    t = torch.as_tensor(t, dtype=torch.float64, device=device).contiguous()
+    if t.shape != (nz,):
+        raise ValueError("tzc1/tzc2 need length nz")
+    return t
+
+
+def _out(ref, t):
+    return torch.zeros_like(ref) if t is None else t
+
+
+def fwd(u, v, w, tzc1, tzc2, tcx, tcy, halo, su=None, sv=None, sw=None):
+    """Forward source terms; returns (su, sv, sw) storage tensors."""
+    nx, ny, nz = _grid(u, halo)
+    su, sv, sw = _out(u, su), _out(u, sv), _out(u, sw)
+    _fields(u, v, w, su, sv, sw)
+    t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
+    _check(lib.pw_advect_fwd(_ptr(u), _ptr(v), _ptr(w), _ptr(t1), _ptr(t2), float(tcx), float(tcy),
+                             nx, ny, nz, halo, _ptr(su), _ptr(sv), _ptr(sw), _dtype_code(u), _stream()))
+    return su, sv, sw
+
+
+def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, gu=None, gv=None, gw=None):
+    """Gather-form adjoint; returns (gu, gv, gw) storage tensors."""
+    nx, ny, nz = _grid(u, halo)
+    gu, gv, gw = _out(u, gu), _out(u, gv), _out(u, gw)
+    _fields(u, v, w, lu, lv, lw, gu, gv, gw)
+    t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
+    _check(lib.pw_advect_adj(_ptr(u), _ptr(v), _ptr(w), _ptr(lu), _ptr(lv), _ptr(lw), _ptr(t1), _ptr(t2),
+                             float(tcx), float(tcy), nx, ny, nz, halo, _ptr(gu), _ptr(gv), _ptr(gw),
+                             _dtype_code(u), _stream()))
+    return gu, gv, gw
+
+
+def fwd_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, out=None):
+    """Forward and adjoint in one launch; returns (su, sv, sw, gu, gv, gw)."""
+    nx, ny, nz = _grid(u, halo)
+    out = [None] * 6 if out is None else list(out)
+    out = [_out(u, t) for t in out]
+    _fields(u, v, w, lu, lv, lw, *out)
+    t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
+    _check(lib.pw_advect_fwd_adj(_ptr(u), _ptr(v), _ptr(w), _ptr(lu), _ptr(lv), _ptr(lw), _ptr(t1),
+                                 _ptr(t2), float(tcx), float(tcy), nx, ny, nz, halo,
+                                 *[_ptr(t) for t in out], _dtype_code(u), _stream()))
+    return tuple(out)
+
+
+def halo_periodic(storage, halo):
+    """Fill the x/y halo columns of ``storage`` periodically, in place."""
+    nx, ny, nz = _grid(storage, halo)
+    _fields(storage)
+    _check(lib.pw_halo_periodic(_ptr(storage), nx, ny, nz, halo, _dtype_code(storage), _stream()))
+    return storage
+
+
+def pad_periodic(interior, halo, out=None):
+    """Storage tensor from a compact interior tensor (periodic x/y halos,
+    zero z halo)."""
+    if not interior.is_cuda or not interior.is_contiguous() or interior.dim() != 3:
+        raise ValueError("interior must be a contiguous 3-D GPU tensor")
+    nx, ny, nz = (int(s) for s in interior.shape)
+    shape = (nx + 2 * halo, ny + 2 * halo, nz + 2 * halo)
+    if out is None:
+        out = torch.empty(shape, dtype=interior.dtype, device=interior.device)
+    elif tuple(out.shape) != shape or out.dtype != interior.dtype or not out.is_contiguous():
+        raise ValueError("out has the wrong shape or dtype")
+    _check(lib.pw_pad_periodic(_ptr(interior), _ptr(out), nx, ny, nz, halo, _dtype_code(interior),
+                               _stream()))
+    return out
+
+
+def fill_uniform(storage, halo, seed, field_id, amp=10.0, zero_lids=False):
+    """Write amp * U[-1, 1) counter-based values into the interior columns of
+    ``storage`` (see inputs.py for the definition); halos are not filled."""
+    nx, ny, nz = _grid(storage, halo)
+    _fields(storage)
+    _check(lib.pw_fill_uniform(_ptr(storage), nx, ny, nz, halo, int(seed), int(field_id), float(amp),
+                               int(bool(zero_lids)), _dtype_code(storage), _stream()))
+    return storage
+
+
+def set_kernel(name):
+    """Select 'auto', 'direct' or 'march'; returns the previous selection."""
+    prev = lib.pw_set_kernel(KERNELS[name])
+    _check(min(prev, 0))
+    return {v: k for k, v in KERNELS.items()}[prev]
+
+
+def get_kernel():
+    return {v: k for k, v in KERNELS.items()}[lib.pw_get_kernel()]
+
+
+def version():
+    return lib.pw_version()

@@ -1,0 +1,142 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pwadvect.h")
+LIB = os.path.join(ROOT, "paper_2010_01545_amd", "libpwadvect.so")
+
+PW_OK, PW_ERR_ARG, PW_ERR_ALIAS, PW_ERR_ALIGN, PW_ERR_SIZE = 0, -1, -2, -3, -4
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pw_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2010_01545_amd.build import build_library
+        build_library()
+    L = ctypes.CDLL(LIB)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.pw_advect_fwd.argtypes = [vp] * 5 + [d, d] + [i] * 4 + [vp] * 3 + [i, vp]
+    L.pw_advect_adj.argtypes = [vp] * 8 + [d, d] + [i] * 4 + [vp] * 3 + [i, vp]
+    L.pw_advect_fwd_adj.argtypes = [vp] * 8 + [d, d] + [i] * 4 + [vp] * 6 + [i, vp]
+    L.pw_pad_periodic.argtypes = [vp, vp] + [i] * 5 + [vp]
+    L.pw_halo_periodic.argtypes = [vp] + [i] * 5 + [vp]
+    L.pw_fill_uniform.argtypes = [vp] + [i] * 4 + [ctypes.c_ulonglong, i, d, i, i, vp]
+    L.pw_last_error.restype = ctypes.c_char_p
+    return L
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert {"pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version(lib):
+    assert lib.pw_version() >= 100
+
+
+# fake, well-aligned, non-overlapping "device" addresses: every case below
+# must be rejected by host-side checks before any of them is dereferenced
+GRID = (8, 6, 64, 2)
+STORAGE = (8 + 4) * (6 + 4) * (64 + 4) * 8
+ADDR = [0x10000000 + q * 0x01000000 for q in range(16)]
+
+
+def fwd(lib, ptrs=None, grid=GRID, dtype=0):
+    p = list(ADDR[:8]) if ptrs is None else ptrs
+    return lib.pw_advect_fwd(p[0], p[1], p[2], p[3], p[4], -0.005, -0.005, *grid, p[5], p[6], p[7],
+                             dtype, None)
+
+
+def test_rejects_null_pointers(lib):
+    for q in range(8):
+        p = list(ADDR[:8])
+        p[q] = None
+        assert fwd(lib, p) == PW_ERR_ARG
+        assert b"NULL" in lib.pw_last_error()
+
+
+@pytest.mark.parametrize("grid", [(0, 6, 64, 2), (8, 0, 64, 2), (8, 6, 1, 2), (8, 6, 64, 0), (-3, 6, 64, 2)])
+def test_rejects_bad_sizes(lib, grid):
+    assert fwd(lib, grid=grid) == PW_ERR_ARG
+
+
+def test_rejects_bad_dtype(lib):
+    assert fwd(lib, dtype=7) == PW_ERR_ARG
+
+
+def test_rejects_size_overflow(lib):
+    assert fwd(lib, grid=(2 ** 31 - 3, 6, 64, 2)) == PW_ERR_SIZE
+    assert fwd(lib, grid=(8, 2 ** 30, 64, 2)) == PW_ERR_SIZE
+
+
+def test_rejects_misaligned(lib):
+    p = list(ADDR[:8])
+    p[6] += 4  # sv misaligned for doubles
+    assert fwd(lib, p) == PW_ERR_ALIGN
+    p = list(ADDR[:8])
+    p[3] += 4  # tzc1 is always double
+    assert fwd(lib, p, dtype=1) == PW_ERR_ALIGN
+
+
+def test_rejects_aliasing(lib):
+    p = list(ADDR[:8])
+    p[5] = p[0]  # su == u
+    assert fwd(lib, p) == PW_ERR_ALIAS
+    p = list(ADDR[:8])
+    p[6] = p[5] + STORAGE // 2  # sv overlaps su
+    assert fwd(lib, p) == PW_ERR_ALIAS
+    p = list(ADDR[:8])
+    p[7] = p[2] + 8  # sw overlaps w
+    assert fwd(lib, p) == PW_ERR_ALIAS
+    # inputs may share memory with each other
+    p = list(ADDR[:8])
+    p[1] = p[0]
+    assert fwd(lib, p) not in (PW_ERR_ALIAS, PW_ERR_ALIGN, PW_ERR_SIZE)
+
+
+def test_adj_and_fused_checks(lib):
+    p = ADDR
+    rc = lib.pw_advect_adj(p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], -0.005, -0.005, *GRID,
+                           p[3], p[8], p[9], 0, None)
+    assert rc == PW_ERR_ALIAS  # gu == lu
+    rc = lib.pw_advect_fwd_adj(p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], -0.005, -0.005, *GRID,
+                               p[8], p[9], p[10], p[11], p[12], p[8], 0, None)
+    assert rc == PW_ERR_ALIAS  # gw == su
+    rc = lib.pw_advect_fwd_adj(p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], -0.005, -0.005, *GRID,
+                               None, p[9], p[10], p[11], p[12], p[13], 0, None)
+    assert rc == PW_ERR_ARG
+
+
+def test_host_pointer_rejected_without_launch(lib):
+    """A host address passes the host-side checks but must be refused as not
+    device memory (on a machine without a GPU the runtime query fails, which
+    is reported the same way)."""
+    bufs = [ctypes.create_string_buffer(STORAGE + 64) for _ in range(6)]
+    tz = [ctypes.create_string_buffer(64 * 8 + 16) for _ in range(2)]
+    al = lambda b: (ctypes.addressof(b) + 15) // 16 * 16
+    p = [al(bufs[0]), al(bufs[1]), al(bufs[2]), al(tz[0]), al(tz[1]), al(bufs[3]), al(bufs[4]), al(bufs[5])]
+    assert fwd(lib, p) == PW_ERR_ARG
+    assert b"device" in lib.pw_last_error()
+
+
+def test_utility_checks(lib):
+    assert lib.pw_halo_periodic(None, 8, 6, 64, 2, 0, None) == PW_ERR_ARG
+    assert lib.pw_pad_periodic(ADDR[0], ADDR[0], 8, 6, 64, 2, 0, None) == PW_ERR_ALIAS
+    assert lib.pw_fill_uniform(ADDR[0], 8, 6, 64, 2, 1, 300, 10.0, 0, 0, None) == PW_ERR_ARG
+    assert lib.pw_set_kernel(9) == PW_ERR_ARG
+    prev = lib.pw_set_kernel(1)
+    assert lib.pw_get_kernel() == 1
+    lib.pw_set_kernel(prev)

@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (stated here and in the design notes):
+  * FP64 forward: normwise max |gpu - oracle| / max |oracle| <= 1e-12 per
+    output field.  The forward kernels evaluate the same expression tree as
+    the oracle without contraction, so the result is also required to be
+    bitwise identical.
+  * FP64 adjoint: <= 1e-12 normwise (the gather sums the same products in a
+    different order than the oracle's scatter).
+  * FP32: every cell within 16 * 2^-24 * T(c) + 1e-30, where T(c) is the sum
+    of |coef| |A| (|B| + |C|) over the cell's terms (the oracle's error
+    magnitude): each term is rounded at most four times and the sum of up to
+    six terms at most six times, so 10 units of 2^-24 bound the arithmetic and
+    the margin covers the rounding of tzc and tcx to FP32.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _helpers import H, host_case, log, normwise, oracle_storage
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+SHAPES = [(32, 32, 64, 0), (5, 7, 3, 1), (33, 17, 65, 2), (3, 3, 3, 3), (1, 1, 64, 4), (2, 3, 2, 5),
+          (1, 9, 64, 6), (17, 1, 64, 7), (40, 24, 64, 8), (7, 130, 64, 9)]
+
+
+@pytest.fixture(scope="module")
+def pw():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2010_01545_amd import pwadvect
+    return pwadvect
+
+
+def kernels(pw):
+    return ["direct", "march"]
+
+
+def to_dev(arrs, dtype):
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype) for a in arrs]
+
+
+def pad_dev(pw, arrs, dtype):
+    return [pw.pad_periodic(t, H) for t in to_dev(arrs, dtype)]
+
+
+def inner(t):
+    return t[H:-H, H:-H, H:-H]
+
+
+def run_fwd(pw, fields, coef, dtype, kernel, sentinel=True):
+    tzc1, tzc2, tcx, tcy = coef
+    st = pad_dev(pw, fields, dtype)
+    outs = [torch.full_like(st[0], float("nan")) if sentinel else torch.zeros_like(st[0]) for _ in range(3)]
+    prev = pw.set_kernel(kernel)
+    try:
+        pw.fwd(*st, torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV), tcx, tcy, H, *outs)
+    finally:
+        pw.set_kernel(prev)
+    torch.cuda.synchronize()
+    return [o.cpu().double().numpy() for o in outs]
+
+
+def march_runs(pw, nz, kernel):
+    return kernel != "march" or nz == 64
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
+def test_fwd_f64_matches_oracle(pw, shape, kernel):
+    nx, ny, nz, seed = shape
+    if not march_runs(pw, nz, kernel):
+        pytest.skip("x-marching kernel is specialised for nz == 64")
+    log("fwd f64 %s %s" % (kernel, shape))
+    fields, _, coef = host_case(nx, ny, nz, seed)
+    ref = oracle.fwd(*oracle_storage(fields), *coef, H)
+    got = run_fwd(pw, fields, coef, torch.float64, kernel)
+    for name, g, r in zip(("su", "sv", "sw"), got, ref):
+        gi, ri = oracle.interior(g, H), oracle.interior(r, H)
+        assert normwise(gi, ri) <= 1e-12, name
+        assert np.array_equal(gi, ri), "%s: %d of %d cells differ" % (name, np.sum(gi != ri), gi.size)
+        # z-halo levels of interior columns are written with 0
+        col = g[H:-H, H:-H, :]
+        assert np.all(col[:, :, :H] == 0) and np.all(col[:, :, -H:] == 0), name
+        # x/y halo columns are never written
+        assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[-H:])), name
+        assert np.all(np.isnan(g[:, :H])) and np.all(np.isnan(g[:, -H:])), name
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("shape", SHAPES[:6], ids=lambda s: "x".join(map(str, s[:3])))
+def test_fwd_f32_error_bound(pw, shape, kernel):
+    nx, ny, nz, seed = shape
+    if not march_runs(pw, nz, kernel):
+        pytest.skip("x-marching kernel is specialised for nz == 64")
+    log("fwd f32 %s %s" % (kernel, shape))
+    fields, _, coef = host_case(nx, ny, nz, seed)
+    f32 = [f.astype(np.float32).astype(np.float64) for f in fields]
+    st = oracle_storage(f32)
+    ref = oracle.fwd(*st, *coef, H)
+    mag = oracle.fwd(*st, *coef, H, abs_bound=True)
+    got = run_fwd(pw, f32, coef, torch.float32, kernel)
+    for name, g, r, t in zip(("su", "sv", "sw"), got, ref, mag):
+        gi, ri, ti = (oracle.interior(a, H) for a in (g, r, t))
+        bound = 16 * 2.0 ** -24 * ti + 1e-30
+        bad = np.abs(gi - ri) > bound
+        assert not np.any(bad), "%s: %d cells exceed the FP32 bound" % (name, np.sum(bad))
+
+
+def run_adj(pw, fields, lams, coef, dtype, kernel, fused=False):
+    tzc1, tzc2, tcx, tcy = coef
+    st = pad_dev(pw, fields, dtype)
+    sl = pad_dev(pw, lams, dtype)
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    prev = pw.set_kernel(kernel)
+    try:
+        if fused:
+            out = pw.fwd_adj(*st, *sl, t1, t2, tcx, tcy, H)
+        else:
+            out = pw.adj(*st, *sl, t1, t2, tcx, tcy, H)
+    finally:
+        pw.set_kernel(prev)
+    torch.cuda.synchronize()
+    return [o.cpu().double().numpy() for o in out]
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
+def test_adj_f64_matches_oracle(pw, shape, kernel):
+    nx, ny, nz, seed = shape
+    if not march_runs(pw, nz, kernel):
+        pytest.skip("x-marching kernel is specialised for nz == 64")
+    log("adj f64 %s %s" % (kernel, shape))
+    fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
+    ref = oracle.adj(*oracle_storage(fields), *oracle_storage(lams), *coef, H)
+    got = run_adj(pw, fields, lams, coef, torch.float64, kernel)
+    for name, g, r in zip(("gu", "gv", "gw"), got, ref):
+        assert normwise(oracle.interior(g, H), oracle.interior(r, H)) <= 1e-12, name
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_fused_equals_separate(pw, kernel, dtype):
+    nx, ny, nz, seed = 40, 24, 64, 11
+    log("fused %s %s" % (kernel, dtype))
+    fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
+    s = run_fwd(pw, fields, coef, dtype, kernel, sentinel=False)
+    g = run_adj(pw, fields, lams, coef, dtype, kernel)
+    f = run_adj(pw, fields, lams, coef, dtype, kernel, fused=True)
+    for a, b in zip(s + g, f):
+        assert np.array_equal(oracle.interior(a, H), oracle.interior(b, H))
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+def test_deterministic(pw, kernel):
+    fields, lams, coef = host_case(33, 20, 64, 12, lam_seed=62)
+    a = run_adj(pw, fields, lams, coef, torch.float64, kernel, fused=True)
+    b = run_adj(pw, fields, lams, coef, torch.float64, kernel, fused=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_march_and_direct_agree_bitwise_on_fwd(pw):
+    fields, _, coef = host_case(64, 48, 64, 13)
+    for dt in (torch.float64, torch.float32):
+        a = run_fwd(pw, fields, coef, dt, "direct", sentinel=False)
+        b = run_fwd(pw, fields, coef, dt, "march", sentinel=False)
+        for x, y in zip(a, b):
+            assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))

@@ -1,0 +1,54 @@
+"""GPU checks of the storage utilities: device generator against the host
+generator (both implement the published SplitMix64 definition), and the
+periodic pad / halo kernels against the oracle's numpy padding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2010_01545_amd import inputs
+from _helpers import H, log
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pw():
+    assert torch.cuda.is_available()
+    from paper_2010_01545_amd import pwadvect
+    return pwadvect
+
+
+@pytest.mark.parametrize("shape", [(8, 6, 64), (5, 3, 7), (1, 1, 2)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_fill_uniform_matches_host_generator(pw, shape, dtype):
+    nx, ny, nz = shape
+    log("fill %s %s" % (shape, dtype))
+    for fid, amp, lids in ((inputs.FIELD_U, 10.0, False), (inputs.FIELD_W, 10.0, True),
+                           (inputs.FIELD_LV, 1.0, False)):
+        st = torch.full((nx + 2 * H, ny + 2 * H, nz + 2 * H), float("nan"), dtype=dtype, device=DEV)
+        pw.fill_uniform(st, H, 7, fid, amp, lids)
+        got = st.cpu().numpy()
+        ref = inputs.uniform_field(7, fid, nx, ny, nz, amp=amp, zero_lids=lids)
+        assert np.array_equal(oracle.interior(got, H), ref.astype(got.dtype))
+        cols = got[H:-H, H:-H]
+        assert np.all(cols[:, :, :H] == 0) and np.all(cols[:, :, -H:] == 0)
+        assert np.all(np.isnan(got[:H])) and np.all(np.isnan(got[:, -H:]))
+
+
+@pytest.mark.parametrize("shape", [(8, 6, 64), (5, 3, 7), (1, 1, 2), (2, 5, 3)])
+@pytest.mark.parametrize("halo", [1, 2, 3])
+def test_pad_and_halo_match_oracle(pw, shape, halo):
+    nx, ny, nz = shape
+    log("pad %s h=%d" % (shape, halo))
+    x = np.random.default_rng(1).standard_normal(shape)
+    ref = oracle.pad_periodic(x, halo)
+    got = pw.pad_periodic(torch.from_numpy(x).to(DEV), halo).cpu().numpy()
+    assert np.array_equal(got, ref)
+    # halo fill in place from a storage array whose halos hold garbage
+    st = torch.from_numpy(ref.copy()).to(DEV)
+    st[:halo] = 1e300
+    st[:, -halo:] = -7.0
+    pw.halo_periodic(st, halo)
+    assert np.array_equal(st.cpu().numpy(), ref)
