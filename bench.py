@@ -197,6 +197,17 @@ def main():
     torch.cuda.init()
     log("bench: %s %dx%dx%d, kernel=%s" % (args.workload, nx, ny, nz, args.kernel))
 
+    if args.only == "copy":
+        # calibration for the HBM byte counters: a plain device copy of a
+        # known size (4 GiB read + 4 GiB written per launch)
+        n = 4 << 30
+        src = torch.empty(n // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration done (%d bytes per launch each way)" % n)
+        return
     if args.only:
         path, dt = args.only.split(":")
         g = Grid(pw, torch, nx, ny, nz, h, torch.float64 if dt == "f64" else torch.float32, seed,

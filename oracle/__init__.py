@@ -38,6 +38,8 @@ def _load(threaded=False):
         lib.pw_oracle_adj.argtypes = [_D] * 8 + [ctypes.c_double, ctypes.c_double] + \
             [ctypes.c_int] * 4 + [_D, _D, _D]
         lib.pw_oracle_adj.restype = None
+        lib.pw_oracle_adj_abs.argtypes = lib.pw_oracle_adj.argtypes
+        lib.pw_oracle_adj_abs.restype = None
         lib.pw_oracle_fold_periodic.argtypes = [_D] + [ctypes.c_int] * 4
         lib.pw_oracle_fold_periodic.restype = None
         _libs[name] = lib
@@ -94,15 +96,18 @@ def fwd(u, v, w, tzc1, tzc2, tcx, tcy, h, threaded=False, abs_bound=False):
     return tuple(outs)
 
 
-def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, h):
+def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, h, abs_bound=False):
     """Gradient of sum(lu*su + lv*sv + lw*sw) over interior cells with respect
     to the interior fields of the x/y-periodic problem, as storage arrays whose
     halo cells are zero.  Fields and multipliers are storage arrays with
-    filled halos (only interior multipliers matter)."""
+    filled halos (only interior multipliers matter).  With ``abs_bound`` the
+    sums of absolute values of the contributing products are returned."""
     nx, ny, nz = _check_storage(h, u, v, w, lu, lv, lw)
     t1, t2 = _profiles(tzc1, tzc2, nz)
     outs = [np.empty_like(u) for _ in range(3)]
-    _load().pw_oracle_adj(_p(u), _p(v), _p(w), _p(lu), _p(lv), _p(lw), _p(t1), _p(t2),
+    lib = _load()
+    f = lib.pw_oracle_adj_abs if abs_bound else lib.pw_oracle_adj
+    f(_p(u), _p(v), _p(w), _p(lu), _p(lv), _p(lw), _p(t1), _p(t2),
                           float(tcx), float(tcy), nx, ny, nz, h,
                           _p(outs[0]), _p(outs[1]), _p(outs[2]))
     return tuple(outs)

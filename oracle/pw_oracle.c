@@ -185,11 +185,20 @@ void pw_oracle_fwd_abs(const double *u, const double *v, const double *w,
  * the scatter, pw_oracle_fold_periodic adds each halo cell into its periodic
  * image and clears the halo.
  */
+static int g_abs_mode = 0; /* set only by pw_oracle_adj_abs */
+
 static void term(double *gA, size_t a, double *gB, size_t b, double *gC, size_t cc,
                  const double *fA, const double *fB, const double *fC,
                  double lam, double coef)
 {
     double A = fA[a], B = fB[b], C = fC[cc];
+    if (g_abs_mode) {
+        A = fabs(A);
+        B = fabs(B);
+        C = fabs(C);
+        lam = fabs(lam);
+        coef = fabs(coef);
+    }
     gA[a] += lam * coef * (B + C);
     gB[b] += lam * coef * A;
     gC[cc] += lam * coef * A;
@@ -281,4 +290,21 @@ void pw_oracle_fold_periodic(double *g, int nx, int ny, int nz, int h)
             }
         }
     }
+}
+
+/*
+ * Rounding-error magnitude companion of pw_oracle_adj: the same scatter and
+ * fold with every coefficient, multiplier and field value replaced by its
+ * absolute value, i.e. for each gradient entry the sum of the absolute values
+ * of all the products that make it up.  Not thread-safe.
+ */
+void pw_oracle_adj_abs(const double *u, const double *v, const double *w,
+                       const double *lu, const double *lv, const double *lw,
+                       const double *tzc1, const double *tzc2, double tcx, double tcy,
+                       int nx, int ny, int nz, int h,
+                       double *gu, double *gv, double *gw)
+{
+    g_abs_mode = 1;
+    pw_oracle_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, nx, ny, nz, h, gu, gv, gw);
+    g_abs_mode = 0;
 }

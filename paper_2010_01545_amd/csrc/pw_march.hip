@@ -1,20 +1,330 @@
-// pw_march.hip -- x-marching kernels (placeholder: not yet available).
+// pw_march.hip -- x-marching PW advection kernels for 64-level columns.
+//
+// Work decomposition.  A workgroup owns a strip of TY consecutive y-columns
+// (contiguous in memory, like the y-batches of the paper's section 3) and a
+// segment of LX consecutive x-planes, which it walks in increasing x (the
+// x-outer loop order of Listing 4).  It has TY + 2 wavefronts: wave w holds
+// y-column j0 - 1 + w, with lane k = level k of that column (nz == 64, so one
+// 64-wide wavefront covers a column and every global access of a wave is one
+// contiguous, coalesced run along z).  Waves 0 and TY + 1 only load the halo
+// columns; waves 1..TY load and compute.
+//
+// Reuse.  Each field (u, v, w and, for the adjoint, lu, lv, lw) is read from
+// HBM once per cell:
+//   * x-neighbours stay in a per-lane register ring of planes p-1 .. p+D+1,
+//     filled D+1 planes ahead of use (software prefetch);
+//   * y-neighbours come from an LDS ring where every wave deposits its
+//     column of the planes the strip needs next;
+//   * k-neighbours come from the neighbouring lane through DPP wavefront
+//     shifts (no memory access);
+//   * the diagonal operands are recycled: u(p-1, j+1) is last step's u(p, j+1)
+//     read, v(p, j-1) is last step's v(p+1, j-1) read.
+// LDS slots.  u- and w-type fields are read only on plane p in step p, so a
+// two-plane ring suffices (step p deposits plane p+1).  v-type fields are
+// also read on plane p+1 (the v(i+1, j-1) operand of su), so they use a
+// three-plane ring (step p deposits plane p+2).  One barrier per step.
+//
+// Block order.  Consecutive workgroup ids are dispatched round-robin over the
+// 8 XCDs; ids are remapped so that each XCD receives a contiguous range of
+// strips, so the halo columns shared by neighbouring strips are read through
+// the same L2.
+#include <cstdlib>
+
 #include "pw_internal.h"
+#include "pw_stencil.h"
 
-template <typename T>
-bool march_supported(const Geom&)
+namespace {
+
+constexpr int NZ = 64;   // levels per column = wavefront width
+constexpr int TY = 6;    // compute columns per workgroup
+constexpr int NCOL = TY + 2;
+constexpr int D = 2;     // planes prefetched ahead of the current xp plane
+
+// Lane k receives lane k-1's value (wavefront shift right by one, DPP).
+__device__ __forceinline__ int dpp_from_below(int x)
 {
-    return false;
+    return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
+}
+// Lane k receives lane k+1's value (wavefront shift left by one, DPP).
+__device__ __forceinline__ int dpp_from_above(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
+}
+
+template <bool BELOW>
+__device__ __forceinline__ float lane_shift(float x)
+{
+    const int v = __float_as_int(x);
+    return __int_as_float(BELOW ? dpp_from_below(v) : dpp_from_above(v));
+}
+
+template <bool BELOW>
+__device__ __forceinline__ double lane_shift(double x)
+{
+    const long long v = __double_as_longlong(x);
+    int lo = (int)(v & 0xffffffffLL);
+    int hi = (int)(v >> 32);
+    lo = BELOW ? dpp_from_below(lo) : dpp_from_above(lo);
+    hi = BELOW ? dpp_from_below(hi) : dpp_from_above(hi);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 template <typename T>
-void launch_fwd_march(const FwdArgs<T>&, const Geom&, hipStream_t)
+__device__ __forceinline__ T below(T x) { return lane_shift<true>(x); }   // level k-1
+template <typename T>
+__device__ __forceinline__ T above(T x) { return lane_shift<false>(x); }  // level k+1
+
+template <typename T, int NF>
+struct MarchArgs {
+    const T* in[NF];   // u, v, w [, lu, lv, lw]
+    T* s[3];           // su, sv, sw (or unused)
+    T* gr[3];          // gu, gv, gw (or unused)
+    const double* tzc1;
+    const double* tzc2;
+    T tcx, tcy;
+};
+
+template <typename T, int NF, bool WS, bool WG>
+__global__ void __launch_bounds__(64 * NCOL)
+march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 {
+    constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
+    constexpr int U = D + 3;        // register ring length
+    __shared__ T s_uw[2 * NT][2][NCOL][NZ];
+    __shared__ T s_v[NT][3][NCOL][NZ];
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+
+    // XCD-aware remap: hardware id b runs on XCD b % 8; give each XCD a
+    // contiguous range of logical ids (strip fastest).
+    const int per = (nblocks + 7) >> 3;
+    const int L = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (L >= nblocks) return;
+    const int strip = L % nstrips;
+    const int seg = L / nstrips;
+    const int j0 = strip * TY;
+    const int ncols = min(TY, g.ny - j0);
+    const int i0 = seg * LX;
+    const int i1 = min(i0 + LX, g.nx);
+    const int j = j0 - 1 + wave;
+    const bool loads = wave <= ncols + 1;        // column j in [j0-1, j0+ncols]
+    const bool comp = wave >= 1 && wave <= ncols; // column j in [j0, j0+ncols)
+    const long long sx = g.sx;
+    const int sy = g.sy;
+    const long long col = (long long)(j + g.h) * sy + g.h + lane;
+
+    // Planes beyond the interior are never used; clamp so that every load
+    // stays inside the storage array (plane nx is the first x halo plane).
+    auto plane_off = [&](int p) -> long long { return (long long)((p < g.nx ? p : g.nx) + g.h) * sx; };
+
+    T R[NF][U];
+    if (loads) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int t = 0; t < D + 2; ++t) R[f][t] = a.in[f][plane_off(i0 - 1 + t) + col];
+    }
+    T carry[NF];
+    if (comp) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (f % 3 == 0) carry[f] = a.in[f][plane_off(i0 - 1) + col + sy];  // F(i0-1, j+1)
+            else if (f % 3 == 1) carry[f] = a.in[f][plane_off(i0) + col - sy]; // F(i0, j-1)
+            else carry[f] = T(0);
+        }
+    }
+    const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, lane, NZ);
+
+    if (loads) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int t = f / 3;
+            if (f % 3 == 0) s_uw[2 * t][i0 & 1][wave][lane] = R[f][1];
+            if (f % 3 == 2) s_uw[2 * t + 1][i0 & 1][wave][lane] = R[f][1];
+            if (f % 3 == 1) {
+                s_v[t][i0 % 3][wave][lane] = R[f][1];
+                s_v[t][(i0 + 1) % 3][wave][lane] = R[f][2];
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int pb = i0; pb < i1; pb += U) {
+        const int vb = pb % 3;
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            const int p = pb + s;
+            if (p >= i1) break;  // uniform over the workgroup
+            const int rm = s % U, rc = (s + 1) % U, rq0 = (s + 2) % U, rq1 = (s + 3) % U;
+            const int rnew = (s + D + 2) % U;
+            const int pu = p & 1;
+            const int v0 = (vb + s) % 3, v1 = (vb + s + 1) % 3, v2 = (vb + s + 2) % 3;
+
+            // prefetch plane p + D + 1
+            if (loads) {
+                const long long off = plane_off(p + D + 1) + col;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) R[f][rnew] = a.in[f][off];
+            }
+
+            if (comp) {
+                Star<T> st[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int t = f / 3;
+                    Star<T>& q = st[f];
+                    q.c = R[f][rc];
+                    q.xm = R[f][rm];
+                    q.xp = R[f][rq0];
+                    q.zm = below(q.c);
+                    q.zp = above(q.c);
+                    if (f % 3 == 0) {            // u-type
+                        q.ym = s_uw[2 * t][pu][wave - 1][lane];
+                        q.yp = s_uw[2 * t][pu][wave + 1][lane];
+                        q.d1 = carry[f];         // F(p-1, j+1)
+                        q.d2 = above(q.xm);      // F(p-1, j, k+1)
+                    } else if (f % 3 == 1) {     // v-type
+                        q.ym = carry[f];         // F(p, j-1)
+                        q.yp = s_v[t][v0][wave + 1][lane];
+                        q.d1 = s_v[t][v1][wave - 1][lane];  // F(p+1, j-1)
+                        q.d2 = above(q.ym);      // F(p, j-1, k+1)
+                    } else {                     // w-type
+                        q.ym = s_uw[2 * t + 1][pu][wave - 1][lane];
+                        q.yp = s_uw[2 * t + 1][pu][wave + 1][lane];
+                        q.d1 = below(q.xp);      // F(p+1, j, k-1)
+                        q.d2 = below(q.yp);      // F(p, j+1, k-1)
+                    }
+                }
+                const long long ob = (long long)(p + g.h) * sx + col;
+                const long long pad = (long long)(p + g.h) * sx + (long long)(j + g.h) * sy +
+                                      (lane < g.h ? lane : NZ + lane);
+                const bool padlane = lane < 2 * g.h;
+                if (WS) {
+                    T su, sv, sw;
+                    pw_fwd_cell(st[0], st[1], st[2], cf, lane, NZ, su, sv, sw);
+                    a.s[0][ob] = su;
+                    a.s[1][ob] = sv;
+                    a.s[2][ob] = sw;
+                    if (padlane) {
+                        a.s[0][pad] = T(0);
+                        a.s[1][pad] = T(0);
+                        a.s[2][pad] = T(0);
+                    }
+                }
+                if (WG) {
+                    T gu, gv, gw;
+                    pw_adj_cell(st[0], st[1], st[2], st[NF - 3], st[NF - 2], st[NF - 1], cf, lane, NZ,
+                                gu, gv, gw);
+                    a.gr[0][ob] = gu;
+                    a.gr[1][ob] = gv;
+                    a.gr[2][ob] = gw;
+                    if (padlane) {
+                        a.gr[0][pad] = T(0);
+                        a.gr[1][pad] = T(0);
+                        a.gr[2][pad] = T(0);
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    if (f % 3 == 0) carry[f] = st[f].yp;  // becomes F((p+1)-1, j+1)
+                    if (f % 3 == 1) carry[f] = st[f].d1;  // becomes F(p+1, j-1)
+                }
+            }
+
+            // deposit: u/w-type plane p+1, v-type plane p+2
+            if (loads) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int t = f / 3;
+                    if (f % 3 == 0) s_uw[2 * t][pu ^ 1][wave][lane] = R[f][rq0];
+                    if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][wave][lane] = R[f][rq0];
+                    if (f % 3 == 1) s_v[t][v2][wave][lane] = R[f][rq1];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct Launch {
+    int LX, nstrips, nblocks, grid;
+};
+
+Launch plan(const Geom& g)
+{
+    Launch l;
+    l.nstrips = (g.ny + TY - 1) / TY;
+    int lx = 0;
+    if (const char* e = std::getenv("PW_MARCH_LX")) lx = std::atoi(e);
+    if (lx <= 0) {
+        // aim for a few thousand workgroups (the GPU holds ~512-768 at once)
+        const int target_segments = (4096 + l.nstrips - 1) / l.nstrips;
+        lx = (g.nx + target_segments - 1) / target_segments;
+        lx = lx < 16 ? 16 : (lx > 256 ? 256 : lx);
+    }
+    l.LX = lx;
+    const int nseg = (g.nx + lx - 1) / lx;
+    l.nblocks = l.nstrips * nseg;
+    l.grid = ((l.nblocks + 7) / 8) * 8;
+    return l;
+}
+
+}  // namespace
+
+template <typename T>
+bool march_supported(const Geom& g)
+{
+    return g.nz == NZ && g.h <= 32;
 }
 
 template <typename T>
-void launch_adj_march(const AdjArgs<T>&, const Geom&, hipStream_t)
+void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
 {
+    MarchArgs<T, 3> m;
+    m.in[0] = a.u;
+    m.in[1] = a.v;
+    m.in[2] = a.w;
+    m.s[0] = a.su;
+    m.s[1] = a.sv;
+    m.s[2] = a.sw;
+    m.gr[0] = m.gr[1] = m.gr[2] = nullptr;
+    m.tzc1 = a.tzc1;
+    m.tzc2 = a.tzc2;
+    m.tcx = a.tcx;
+    m.tcy = a.tcy;
+    const Launch l = plan(g);
+    hipLaunchKernelGGL((march_kernel<T, 3, true, false>), dim3(l.grid), dim3(64 * NCOL), 0, s, m, g,
+                       l.LX, l.nstrips, l.nblocks);
+}
+
+template <typename T>
+void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
+{
+    MarchArgs<T, 6> m;
+    m.in[0] = a.u;
+    m.in[1] = a.v;
+    m.in[2] = a.w;
+    m.in[3] = a.lu;
+    m.in[4] = a.lv;
+    m.in[5] = a.lw;
+    m.s[0] = a.su;
+    m.s[1] = a.sv;
+    m.s[2] = a.sw;
+    m.gr[0] = a.gu;
+    m.gr[1] = a.gv;
+    m.gr[2] = a.gw;
+    m.tzc1 = a.tzc1;
+    m.tzc2 = a.tzc2;
+    m.tcx = a.tcx;
+    m.tcy = a.tcy;
+    const Launch l = plan(g);
+    if (a.su)
+        hipLaunchKernelGGL((march_kernel<T, 6, true, true>), dim3(l.grid), dim3(64 * NCOL), 0, s, m, g,
+                           l.LX, l.nstrips, l.nblocks);
+    else
+        hipLaunchKernelGGL((march_kernel<T, 6, false, true>), dim3(l.grid), dim3(64 * NCOL), 0, s, m, g,
+                           l.LX, l.nstrips, l.nblocks);
 }
 
 template bool march_supported<double>(const Geom&);

@@ -5,8 +5,9 @@
 // Forward: su follows Listing 1 of section 2.1 with Fortran's left-to-right
 // association; sv is its x<->y transpose analogue; sw is the same
 // upwind-value-times-face-sum scheme staggered in z (levels 1..nz-2).
-// FP contraction is switched off inside these functions so that the FP64
-// forward rounds exactly like a plain evaluation of that expression.
+// FP contraction is switched off inside these functions: the FP64 forward
+// then rounds exactly like a plain evaluation of that expression, and every
+// kernel variant gives bitwise identical results.
 //
 // Operands come as "stars": the value at the cell, its six face neighbours
 // and two diagonal neighbours whose position depends on the field:
@@ -83,18 +84,21 @@ __device__ __forceinline__ void pw_fwd_cell(const Star<T>& u, const Star<T>& v, 
 //   A2(q): 1 <= q <= nz-2   (su, sv tzc2 terms; every sw term)
 // Masked contributions are selected away (never multiplied by zero), so
 // z-halo values that are read but unused cannot leak NaN into the result.
+// Contraction is off here too, so every kernel that uses this function
+// (fused or not, direct or x-marching) rounds identically.
 template <typename T>
 __device__ __forceinline__ void pw_adj_cell(const Star<T>& u, const Star<T>& v, const Star<T>& w,
                                             const Star<T>& lu, const Star<T>& lv, const Star<T>& lw,
                                             const LevelCoef<T>& cf, int k, int nz,
                                             T& gu, T& gv, T& gw)
 {
+#pragma clang fp contract(off)
     const T tcx = cf.tcx, tcy = cf.tcy;
     const bool a1k = (k >= 1);                 // A1(k)
     const bool a2k = (k >= 1) && (k <= nz - 2); // A2(k)
     const bool a1kp = (k <= nz - 2);           // A1(k+1)
     const bool a2km = (k >= 2);                // A2(k-1)
-    const bool a2kp = (k >= 1) && (k <= nz - 3); // A2(k+1) (k+1 >= 1 always; k >= 0)
+    const bool a2kp = (k <= nz - 3);           // A2(k+1) (k+1 >= 1 always)
     const T zero = T(0);
     T g, t;
 
