@@ -36,9 +36,6 @@
 namespace {
 
 constexpr int NZ = 64;   // levels per column = wavefront width
-constexpr int TY = 6;    // compute columns per workgroup
-constexpr int NCOL = TY + 2;
-constexpr int D = 2;     // planes prefetched ahead of the current xp plane
 
 // Lane k receives lane k-1's value (wavefront shift right by one, DPP).
 __device__ __forceinline__ int dpp_from_below(int x)
@@ -84,10 +81,14 @@ struct MarchArgs {
     T tcx, tcy;
 };
 
-template <typename T, int NF, bool WS, bool WG>
-__global__ void __launch_bounds__(64 * NCOL)
+// TY: compute columns per workgroup (TY + 2 wavefronts); D: planes
+// prefetched beyond the current xp plane (D >= 2).
+template <typename T, int NF, bool WS, bool WG, int TY, int D>
+__global__ void __launch_bounds__(64 * (TY + 2))
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 {
+    static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
+    constexpr int NCOL = TY + 2;
     constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
     constexpr int U = D + 3;        // register ring length
     __shared__ T s_uw[2 * NT][2][NCOL][NZ];
@@ -251,23 +252,74 @@ struct Launch {
     int LX, nstrips, nblocks, grid;
 };
 
-Launch plan(const Geom& g)
+Launch plan(const Geom& g, int TY)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
     int lx = 0;
     if (const char* e = std::getenv("PW_MARCH_LX")) lx = std::atoi(e);
     if (lx <= 0) {
-        // aim for a few thousand workgroups (the GPU holds ~512-768 at once)
-        const int target_segments = (4096 + l.nstrips - 1) / l.nstrips;
-        lx = (g.nx + target_segments - 1) / target_segments;
-        lx = lx < 16 ? 16 : (lx > 256 ? 256 : lx);
+        // Segments of up to 128 planes (measured best at 4096 x 4096 x 64);
+        // shorter ones on small grids so that about 8192 workgroups exist.
+        const long long want = ((long long)g.nx * l.nstrips + 8191) / 8192;
+        lx = want < 16 ? 16 : (want > 128 ? 128 : (int)want);
     }
     l.LX = lx;
     const int nseg = (g.nx + lx - 1) / lx;
     l.nblocks = l.nstrips * nseg;
     l.grid = ((l.nblocks + 7) / 8) * 8;
     return l;
+}
+
+// Strip width and prefetch depth of each variant.  Variants whose LDS ring
+// would exceed 64 KiB for a given field count fall back to variant 0.
+constexpr int kVariants = 4;
+constexpr int kTY[kVariants] = {6, 6, 14, 14};
+constexpr int kD[kVariants] = {2, 4, 2, 4};
+
+template <typename T, int NF, int TY>
+constexpr int lds_bytes()
+{
+    return (int)sizeof(T) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
+}
+
+template <typename T, int NF, bool WS, bool WG, int TY, int D>
+void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
+{
+    if constexpr (lds_bytes<T, NF, TY>() <= 65536) {
+        const Launch l = plan(g, TY);
+        hipLaunchKernelGGL((march_kernel<T, NF, WS, WG, TY, D>), dim3(l.grid), dim3(64 * (TY + 2)), 0, s, m,
+                           g, l.LX, l.nstrips, l.nblocks);
+    } else {
+        go<T, NF, WS, WG, kTY[0], kD[0]>(m, g, s);
+    }
+}
+
+// Default variant per element type and field count, from sweeps on MI355X at
+// 4096 x 4096 x 64: the forward runs best with 14-column strips (fewer halo
+// waves per computed column); the six-field kernels keep 6-column strips (the
+// FP64 14-column ring does not fit 64 KiB of LDS, and the FP32 one measured
+// slower).  PW_MARCH_VARIANT=0..3 overrides the choice for sweeps.
+template <typename T, int NF>
+int default_variant()
+{
+    return NF == 3 ? 2 : 0;
+}
+
+template <typename T, int NF, bool WS, bool WG>
+void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
+{
+    int v = default_variant<T, NF>();
+    if (const char* e = std::getenv("PW_MARCH_VARIANT")) {
+        const int q = std::atoi(e);
+        if (q >= 0 && q < kVariants) v = q;
+    }
+    switch (v) {
+    case 1: go<T, NF, WS, WG, kTY[1], kD[1]>(m, g, s); break;
+    case 2: go<T, NF, WS, WG, kTY[2], kD[2]>(m, g, s); break;
+    case 3: go<T, NF, WS, WG, kTY[3], kD[3]>(m, g, s); break;
+    default: go<T, NF, WS, WG, kTY[0], kD[0]>(m, g, s); break;
+    }
 }
 
 }  // namespace
@@ -293,9 +345,7 @@ void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
     m.tzc2 = a.tzc2;
     m.tcx = a.tcx;
     m.tcy = a.tcy;
-    const Launch l = plan(g);
-    hipLaunchKernelGGL((march_kernel<T, 3, true, false>), dim3(l.grid), dim3(64 * NCOL), 0, s, m, g,
-                       l.LX, l.nstrips, l.nblocks);
+    dispatch<T, 3, true, false>(m, g, s);
 }
 
 template <typename T>
@@ -318,13 +368,10 @@ void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
     m.tzc2 = a.tzc2;
     m.tcx = a.tcx;
     m.tcy = a.tcy;
-    const Launch l = plan(g);
     if (a.su)
-        hipLaunchKernelGGL((march_kernel<T, 6, true, true>), dim3(l.grid), dim3(64 * NCOL), 0, s, m, g,
-                           l.LX, l.nstrips, l.nblocks);
+        dispatch<T, 6, true, true>(m, g, s);
     else
-        hipLaunchKernelGGL((march_kernel<T, 6, false, true>), dim3(l.grid), dim3(64 * NCOL), 0, s, m, g,
-                           l.LX, l.nstrips, l.nblocks);
+        dispatch<T, 6, false, true>(m, g, s);
 }
 
 template bool march_supported<double>(const Geom&);

@@ -13,6 +13,8 @@ Tolerances (stated here and in the design notes):
     six terms at most six times, so 10 units of 2^-24 bound the arithmetic and
     the margin covers the rounding of tzc and tcx to FP32.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -194,4 +196,32 @@ def test_march_and_direct_agree_bitwise(pw, dtype):
     a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
     b = run_adj(pw, fields, lams, coef, dtype, "march", fused=True)
     for x, y in zip(a, b):
+        assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_every_march_variant_matches_direct(pw, variant, dtype):
+    """Each strip-width / prefetch-depth variant of the x-marching kernel (and
+    a short march length, so several x-segments meet) gives the direct
+    kernel's bits, forward, adjoint and fused."""
+    fields, lams, coef = host_case(45, 31, 64, 14, lam_seed=64)
+    ref_f = run_fwd(pw, fields, coef, dtype, "direct", sentinel=False)
+    ref_a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
+    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
+    os.environ["PW_MARCH_VARIANT"] = variant
+    os.environ["PW_MARCH_LX"] = "7"
+    try:
+        got_f = run_fwd(pw, fields, coef, dtype, "march", sentinel=False)
+        got_a = run_adj(pw, fields, lams, coef, dtype, "march", fused=True)
+        got_g = run_adj(pw, fields, lams, coef, dtype, "march", fused=False)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for x, y in zip(ref_f + ref_a, got_f + got_a):
+        assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
+    for x, y in zip(ref_a[3:], got_g):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
