@@ -14,28 +14,38 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Star of field f around storage element b; DIAG selects the field's two
-// diagonal neighbours (0: u, 1: v, 2: w; see pw_stencil.h).
-template <typename T, int DIAG>
-__device__ __forceinline__ Star<T> load_star(const T* __restrict__ f, long long b, long long sx, int sy)
+// Star of field f around storage element b at interior level k; DIAG
+// selects the field's two diagonal neighbours (0: u, 1: v, 2: w; see
+// pw_stencil.h).  Operands on levels outside 0..nz-1 (z halo, whatever it
+// holds) are replaced by 0; with LAM the adjoint multiplier's level mask is
+// applied as well (lu, lv live on 1..nz-1, lw on 1..nz-2).
+template <typename T, int DIAG, bool LAM>
+__device__ __forceinline__ Star<T> load_star(const T* __restrict__ f, long long b, long long sx, int sy,
+                                             int k, int nz)
 {
+    auto live = [&](int level) -> bool {
+        if (LAM) return DIAG == 2 ? lam_w_live(level, nz) : lam_uv_live(level, nz);
+        return level >= 0 && level <= nz - 1;
+    };
+    const bool lk = live(k), lkm = live(k - 1), lkp = live(k + 1);
+    const T z = T(0);
     Star<T> s;
-    s.c = f[b];
-    s.xm = f[b - sx];
-    s.xp = f[b + sx];
-    s.ym = f[b - sy];
-    s.yp = f[b + sy];
-    s.zm = f[b - 1];
-    s.zp = f[b + 1];
+    s.c = lk ? f[b] : z;
+    s.xm = lk ? f[b - sx] : z;
+    s.xp = lk ? f[b + sx] : z;
+    s.ym = lk ? f[b - sy] : z;
+    s.yp = lk ? f[b + sy] : z;
+    s.zm = lkm ? f[b - 1] : z;
+    s.zp = lkp ? f[b + 1] : z;
     if (DIAG == 0) {
-        s.d1 = f[b - sx + sy];
-        s.d2 = f[b - sx + 1];
+        s.d1 = lk ? f[b - sx + sy] : z;
+        s.d2 = lkp ? f[b - sx + 1] : z;
     } else if (DIAG == 1) {
-        s.d1 = f[b + sx - sy];
-        s.d2 = f[b - sy + 1];
+        s.d1 = lk ? f[b + sx - sy] : z;
+        s.d2 = lkp ? f[b - sy + 1] : z;
     } else {
-        s.d1 = f[b + sx - 1];
-        s.d2 = f[b + sy - 1];
+        s.d1 = lkm ? f[b + sx - 1] : z;
+        s.d2 = lkm ? f[b + sy - 1] : z;
     }
     return s;
 }
@@ -56,9 +66,9 @@ __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g
             a.sw[b] = T(0);
             continue;
         }
-        const Star<T> u = load_star<T, 0>(a.u, b, g.sx, g.sy);
-        const Star<T> v = load_star<T, 1>(a.v, b, g.sx, g.sy);
-        const Star<T> w = load_star<T, 2>(a.w, b, g.sx, g.sy);
+        const Star<T> u = load_star<T, 0, false>(a.u, b, g.sx, g.sy, k, g.nz);
+        const Star<T> v = load_star<T, 1, false>(a.v, b, g.sx, g.sy, k, g.nz);
+        const Star<T> w = load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz);
         const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, k, g.nz);
         T su, sv, sw;
         pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
@@ -89,12 +99,12 @@ __global__ void __launch_bounds__(kBlock) adj_direct_kernel(AdjArgs<T> a, Geom g
             a.gw[b] = T(0);
             continue;
         }
-        const Star<T> u = load_star<T, 0>(a.u, b, g.sx, g.sy);
-        const Star<T> v = load_star<T, 1>(a.v, b, g.sx, g.sy);
-        const Star<T> w = load_star<T, 2>(a.w, b, g.sx, g.sy);
-        const Star<T> lu = load_star<T, 0>(a.lu, b, g.sx, g.sy);
-        const Star<T> lv = load_star<T, 1>(a.lv, b, g.sx, g.sy);
-        const Star<T> lw = load_star<T, 2>(a.lw, b, g.sx, g.sy);
+        const Star<T> u = load_star<T, 0, false>(a.u, b, g.sx, g.sy, k, g.nz);
+        const Star<T> v = load_star<T, 1, false>(a.v, b, g.sx, g.sy, k, g.nz);
+        const Star<T> w = load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz);
+        const Star<T> lu = load_star<T, 0, true>(a.lu, b, g.sx, g.sy, k, g.nz);
+        const Star<T> lv = load_star<T, 1, true>(a.lv, b, g.sx, g.sy, k, g.nz);
+        const Star<T> lw = load_star<T, 2, true>(a.lw, b, g.sx, g.sy, k, g.nz);
         const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, k, g.nz);
         if (FUSED) {
             T su, sv, sw;

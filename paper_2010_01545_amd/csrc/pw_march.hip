@@ -40,12 +40,12 @@ constexpr int NZ = 64;   // levels per column = wavefront width
 // Lane k receives lane k-1's value (wavefront shift right by one, DPP).
 __device__ __forceinline__ int dpp_from_below(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
 }
 // Lane k receives lane k+1's value (wavefront shift left by one, DPP).
 __device__ __forceinline__ int dpp_from_above(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true);
 }
 
 template <bool BELOW>
@@ -71,6 +71,45 @@ __device__ __forceinline__ T below(T x) { return lane_shift<true>(x); }   // lev
 template <typename T>
 __device__ __forceinline__ T above(T x) { return lane_shift<false>(x); }  // level k+1
 
+// Raw buffer access to one storage column: the descriptor's base is the
+// column start (wave-uniform, scalar registers) and its record count the
+// column's byte length, or 0 for a wave that must not touch memory.  Loads
+// outside the record range return 0 and stores outside it are dropped, so
+// every wave issues the same sequence of memory instructions, with no
+// branches around them; that keeps the compiler's wait counts exact, which
+// the register prefetch relies on.  Word 3 is the gfx9 raw-buffer format.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr unsigned kOutOfRange = 0x40000000u;  // byte offset beyond any column
+
+__device__ __forceinline__ rsrc_t column_rsrc(const void* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kRsrcWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buf_load<double>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+using u32x2 = unsigned int __attribute__((vector_size(8)));
+__device__ __forceinline__ void buf_store(double x, rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(float x, rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, (int)off, 0, 0);
+}
+
 template <typename T, int NF>
 struct MarchArgs {
     const T* in[NF];   // u, v, w [, lu, lv, lw]
@@ -94,7 +133,10 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     __shared__ T s_uw[2 * NT][2][NCOL][NZ];
     __shared__ T s_v[NT][3][NCOL][NZ];
 
-    const int wave = threadIdx.x >> 6;
+    // the wave index is uniform over a wavefront: keep it (and every address
+    // part derived from it) in scalar registers, so that a global access is a
+    // scalar base plus the lane offset
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
 
     // XCD-aware remap: hardware id b runs on XCD b % 8; give each XCD a
@@ -113,31 +155,48 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     const bool comp = wave >= 1 && wave <= ncols; // column j in [j0, j0+ncols)
     const long long sx = g.sx;
     const int sy = g.sy;
-    const long long col = (long long)(j + g.h) * sy + g.h + lane;
+    const int colbytes = g.Sz * (int)sizeof(T);
+    const int ldbytes = loads ? colbytes : 0;     // waves past the strip read zeros
+    const int stbytes = comp ? colbytes : 0;      // only computing waves write
+    // storage column (plane p, column j + dj), as a pointer to its first level
+    auto column = [&](const T* f, int p, int dj) -> const T* {
+        const int pc = p < g.nx ? p : g.nx;       // planes past the end are never used
+        return f + ((long long)(pc + g.h) * sx + (long long)(j + dj + g.h) * sy);
+    };
+    const unsigned voff = (unsigned)(g.h + lane) * (unsigned)sizeof(T);  // interior level `lane`
+    // z-halo levels of an output column: lanes 0..h-1 bottom, h..2h-1 top
+    const unsigned vpad = lane < g.h ? (unsigned)lane * (unsigned)sizeof(T)
+                        : (lane < 2 * g.h ? (unsigned)(NZ + lane) * (unsigned)sizeof(T) : kOutOfRange);
 
-    // Planes beyond the interior are never used; clamp so that every load
-    // stays inside the storage array (plane nx is the first x halo plane).
-    auto plane_off = [&](int p) -> long long { return (long long)((p < g.nx ? p : g.nx) + g.h) * sx; };
+    // Multipliers are used with their level masks applied (see
+    // pw_stencil.h): every operand of the gather is then a masked value, a
+    // copy of one, or a DPP shift of one (shifts across the column ends read
+    // 0).  The mask is applied where a freshly loaded plane is first used, so
+    // that the prefetch is not waited for at the load.
+    const bool live_uv = lam_uv_live(lane, NZ), live_w = lam_w_live(lane, NZ);
+    auto mask = [&](int f, T x) -> T {
+        if (f < 3) return x;
+        return ((f == 5) ? live_w : live_uv) ? x : T(0);
+    };
+    auto ld = [&](int f, int p, int dj, int bytes) -> T {
+        return buf_load<T>(column_rsrc(column(a.in[f], p, dj), bytes), voff);
+    };
 
     T R[NF][U];
-    if (loads) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int t = 0; t < D + 2; ++t) R[f][t] = a.in[f][plane_off(i0 - 1 + t) + col];
-    }
+        for (int t = 0; t < D + 2; ++t) R[f][t] = mask(f, ld(f, i0 - 1 + t, 0, ldbytes));
     T carry[NF];
-    if (comp) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            if (f % 3 == 0) carry[f] = a.in[f][plane_off(i0 - 1) + col + sy];  // F(i0-1, j+1)
-            else if (f % 3 == 1) carry[f] = a.in[f][plane_off(i0) + col - sy]; // F(i0, j-1)
-            else carry[f] = T(0);
-        }
+    for (int f = 0; f < NF; ++f) {
+        if (f % 3 == 0) carry[f] = mask(f, ld(f, i0 - 1, 1, stbytes));   // F(i0-1, j+1)
+        else if (f % 3 == 1) carry[f] = mask(f, ld(f, i0, -1, stbytes)); // F(i0, j-1)
+        else carry[f] = T(0);
     }
     const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, lane, NZ);
 
-    if (loads) {
+    {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int t = f / 3;
@@ -163,13 +222,18 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
             const int v0 = (vb + s) % 3, v1 = (vb + s + 1) % 3, v2 = (vb + s + 2) % 3;
 
             // prefetch plane p + D + 1
-            if (loads) {
-                const long long off = plane_off(p + D + 1) + col;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) R[f][rnew] = a.in[f][off];
+            for (int f = 0; f < NF; ++f) R[f][rnew] = ld(f, p + D + 1, 0, ldbytes);
+
+            // first use of planes p+1 (all fields) and p+2 (v-type deposit)
+#pragma unroll
+            for (int f = 3; f < NF; ++f) {
+                R[f][rq0] = mask(f, R[f][rq0]);
+                if (f % 3 == 1) R[f][rq1] = mask(f, R[f][rq1]);
             }
 
-            if (comp) {
+            T out[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+            if (comp) {  // arithmetic only: no memory access inside the branch
                 Star<T> st[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -197,35 +261,10 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                         q.d2 = below(q.yp);      // F(p, j+1, k-1)
                     }
                 }
-                const long long ob = (long long)(p + g.h) * sx + col;
-                const long long pad = (long long)(p + g.h) * sx + (long long)(j + g.h) * sy +
-                                      (lane < g.h ? lane : NZ + lane);
-                const bool padlane = lane < 2 * g.h;
-                if (WS) {
-                    T su, sv, sw;
-                    pw_fwd_cell(st[0], st[1], st[2], cf, lane, NZ, su, sv, sw);
-                    a.s[0][ob] = su;
-                    a.s[1][ob] = sv;
-                    a.s[2][ob] = sw;
-                    if (padlane) {
-                        a.s[0][pad] = T(0);
-                        a.s[1][pad] = T(0);
-                        a.s[2][pad] = T(0);
-                    }
-                }
-                if (WG) {
-                    T gu, gv, gw;
+                if (WS) pw_fwd_cell(st[0], st[1], st[2], cf, lane, NZ, out[0], out[1], out[2]);
+                if (WG)
                     pw_adj_cell(st[0], st[1], st[2], st[NF - 3], st[NF - 2], st[NF - 1], cf, lane, NZ,
-                                gu, gv, gw);
-                    a.gr[0][ob] = gu;
-                    a.gr[1][ob] = gv;
-                    a.gr[2][ob] = gw;
-                    if (padlane) {
-                        a.gr[0][pad] = T(0);
-                        a.gr[1][pad] = T(0);
-                        a.gr[2][pad] = T(0);
-                    }
-                }
+                                out[3], out[4], out[5]);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     if (f % 3 == 0) carry[f] = st[f].yp;  // becomes F((p+1)-1, j+1)
@@ -233,15 +272,23 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 }
             }
 
-            // deposit: u/w-type plane p+1, v-type plane p+2
-            if (loads) {
+            // outputs of plane p: interior levels and zero z-halo levels
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const int t = f / 3;
-                    if (f % 3 == 0) s_uw[2 * t][pu ^ 1][wave][lane] = R[f][rq0];
-                    if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][wave][lane] = R[f][rq0];
-                    if (f % 3 == 1) s_v[t][v2][wave][lane] = R[f][rq1];
-                }
+            for (int q = 0; q < 6; ++q) {
+                if ((q < 3 && !WS) || (q >= 3 && !WG)) continue;
+                T* const dst = q < 3 ? a.s[q] : a.gr[q - 3];
+                const rsrc_t r = column_rsrc(column(dst, p, 0), stbytes);
+                buf_store(out[q], r, voff);
+                buf_store(T(0), r, vpad);
+            }
+
+            // deposit: u/w-type plane p+1, v-type plane p+2
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const int t = f / 3;
+                if (f % 3 == 0) s_uw[2 * t][pu ^ 1][wave][lane] = R[f][rq0];
+                if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][wave][lane] = R[f][rq0];
+                if (f % 3 == 1) s_v[t][v2][wave][lane] = R[f][rq1];
             }
             __syncthreads();
         }
@@ -296,14 +343,14 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 }
 
 // Default variant per element type and field count, from sweeps on MI355X at
-// 4096 x 4096 x 64: the forward runs best with 14-column strips (fewer halo
-// waves per computed column); the six-field kernels keep 6-column strips (the
-// FP64 14-column ring does not fit 64 KiB of LDS, and the FP32 one measured
-// slower).  PW_MARCH_VARIANT=0..3 overrides the choice for sweeps.
+// 4096 x 4096 x 64: 14-column strips (fewer halo waves per computed column)
+// wherever the LDS ring fits 64 KiB; the FP64 six-field kernels keep
+// 6-column strips.  Deeper prefetch (D = 4) measured no faster.
+// PW_MARCH_VARIANT=0..3 overrides the choice for sweeps.
 template <typename T, int NF>
 int default_variant()
 {
-    return NF == 3 ? 2 : 0;
+    return (NF == 3 || sizeof(T) == 4) ? 2 : 0;
 }
 
 template <typename T, int NF, bool WS, bool WG>

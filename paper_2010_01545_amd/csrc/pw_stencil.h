@@ -73,19 +73,31 @@ __device__ __forceinline__ void pw_fwd_cell(const Star<T>& u, const Star<T>& v, 
     sw = (k == 0 || top) ? T(0) : s;
 }
 
+// One rounding: a * b + c.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Level masks of the adjoint multipliers.  A term of output cell c exists
+// only on c's level range: su, sv terms with tcx, tcy, tzc1 on 1..nz-1; the
+// su, sv tzc2 terms and every sw term on 1..nz-2.  The kernels store the
+// multipliers with these ranges applied (lu, lv zero on level 0; lw zero on
+// levels 0 and nz-1; any operand outside 0..nz-1 zero), which encodes every
+// term's range except that of the su, sv tzc2 terms read at the cell's own
+// level; pw_adj_cell applies that one through the tzc2[k] coefficient.
+__device__ __forceinline__ bool lam_uv_live(int level, int nz) { return level >= 1 && level <= nz - 1; }
+__device__ __forceinline__ bool lam_w_live(int level, int nz) { return level >= 1 && level <= nz - 2; }
+
 // Gather-form adjoint of one interior cell p at level k: the derivative of
 // L = sum_c lu(c) su(c) + lv(c) sv(c) + lw(c) sw(c) with respect to u(p),
 // v(p), w(p).  Each output term coef * A * (B + C) of a cell c that reads
 // the field at p contributes lam(c) * coef * (B + C) when A sits at p and
-// lam(c) * coef * A when B or C does; the sum below lists, for each of the
-// eighteen terms of the scheme, every cell c = p - offset that reads p.
-// A contribution is kept only when its term exists at c's level:
-//   A1(q): 1 <= q <= nz-1   (su, sv terms with tcx, tcy, tzc1)
-//   A2(q): 1 <= q <= nz-2   (su, sv tzc2 terms; every sw term)
-// Masked contributions are selected away (never multiplied by zero), so
-// z-halo values that are read but unused cannot leak NaN into the result.
-// Contraction is off here too, so every kernel that uses this function
-// (fused or not, direct or x-marching) rounds identically.
+// lam(c) * coef * A when B or C does.  Below, for each coefficient, the
+// contributions of all cells c = p - offset that read p are summed (with A
+// and C coinciding in the self-advection terms, giving the 2 * F(p) sums);
+// the bracket names the output term and the operand that sits at p.
+// The multipliers must carry the level masks described above.  Evaluation
+// uses explicit fused multiply-adds in a fixed order, so every kernel that
+// calls this function produces the same bits.
 template <typename T>
 __device__ __forceinline__ void pw_adj_cell(const Star<T>& u, const Star<T>& v, const Star<T>& w,
                                             const Star<T>& lu, const Star<T>& lv, const Star<T>& lw,
@@ -93,118 +105,86 @@ __device__ __forceinline__ void pw_adj_cell(const Star<T>& u, const Star<T>& v, 
                                             T& gu, T& gv, T& gw)
 {
 #pragma clang fp contract(off)
-    const T tcx = cf.tcx, tcy = cf.tcy;
-    const bool a1k = (k >= 1);                 // A1(k)
-    const bool a2k = (k >= 1) && (k <= nz - 2); // A2(k)
-    const bool a1kp = (k <= nz - 2);           // A1(k+1)
-    const bool a2km = (k >= 2);                // A2(k-1)
-    const bool a2kp = (k <= nz - 3);           // A2(k+1) (k+1 >= 1 always)
-    const T zero = T(0);
-    T g, t;
+    const T two = T(2);
+    // tzc2[k] multiplies only terms of cells at level k, where the su, sv
+    // tzc2 terms need k <= nz-2 (the sw terms are masked through lw)
+    const T t2k = (k <= nz - 2) ? cf.t2k : T(0);
+    T x, y, z1, z2;
 
     // ---- d L / d u(p)
-    g = zero;
-    // su, +tcx u(c-x)(u(c)+u(c-x)):  c = p+x (A and C), c = p (B)
-    t = tcx * (lu.xp * (u.xp + u.c) + lu.c * u.xm + lu.xp * u.c);
-    g += a1k ? t : zero;
-    // su, -tcx u(c+x)(u(c)+u(c+x)):  c = p-x (A and C), c = p (B)
-    t = tcx * (lu.xm * (u.xm + u.c) + lu.c * u.xp + lu.xm * u.c);
-    g -= a1k ? t : zero;
-    // su, +tcy u(c-y)(v(c-y)+v(c+x-y)): A at p, c = p+y
-    t = tcy * (lu.yp * (v.c + v.xp));
-    g += a1k ? t : zero;
-    // su, -tcy u(c+y)(v(c)+v(c+x)): A at p, c = p-y
-    t = tcy * (lu.ym * (v.ym + v.d1));
-    g -= a1k ? t : zero;
-    // su, +tzc1 u(c-z)(w(c-z)+w(c+x-z)): A at p, c = p+z
-    t = cf.t1kp * (lu.zp * (w.c + w.xp));
-    g += a1kp ? t : zero;
-    // su, -tzc2 u(c+z)(w(c)+w(c+x)): A at p, c = p-z
-    t = cf.t2km * (lu.zm * (w.zm + w.d1));
-    g -= a2km ? t : zero;
-    // sv, +tcx v(c-x)(u(c-x)+u(c-x+y)): B at p (c = p+x), C at p (c = p+x-y)
-    t = tcx * (lv.xp * v.c + lv.d1 * v.ym);
-    g += a1k ? t : zero;
-    // sv, -tcx v(c+x)(u(c)+u(c+y)): B at p (c = p), C at p (c = p-y)
-    t = tcx * (lv.c * v.xp + lv.ym * v.d1);
-    g -= a1k ? t : zero;
-    // sw, +tcx w(c-x)(u(c-x)+u(c-x+z)): B at p (c = p+x), C at p (c = p+x-z)
-    t = tcx * (a2k ? lw.xp * w.c : zero) + tcx * (a2km ? lw.d1 * w.zm : zero);
-    g += t;
-    // sw, -tcx w(c+x)(u(c)+u(c+z)): B at p (c = p), C at p (c = p-z)
-    t = tcx * (a2k ? lw.c * w.xp : zero) + tcx * (a2km ? lw.zm * w.d1 : zero);
-    g -= t;
-    gu = g;
+    // tcx: su x term (A, C at c = p+x; B at c = p) minus its mirror at p-x,
+    //      sv x terms (B at c = p+x / p; C at c = p+x-y / p-y),
+    //      sw x terms (B at c = p+x / p; C at c = p+x-z / p-z);
+    // three independent partial sums, then combined
+    x = lu.xp * fmad(two, u.c, u.xp);
+    x = fmad(lu.c, u.xm, x);
+    x = fmad(-lu.xm, fmad(two, u.c, u.xm), x);
+    x = fmad(-lu.c, u.xp, x);
+    y = lv.xp * v.c;
+    y = fmad(lv.d1, v.ym, y);
+    y = fmad(-lv.c, v.xp, y);
+    y = fmad(-lv.ym, v.d1, y);
+    z1 = lw.xp * w.c;
+    z1 = fmad(lw.d1, w.zm, z1);
+    z1 = fmad(-lw.c, w.xp, z1);
+    z1 = fmad(-lw.zm, w.d1, z1);
+    const T xu = (x + y) + z1;
+    // tcy: su y terms, A at c = p+y and c = p-y
+    y = lu.yp * (v.c + v.xp);
+    y = fmad(-lu.ym, v.ym + v.d1, y);
+    // tzc1[k+1]: su z term, A at c = p+z;  tzc2[k-1]: A at c = p-z
+    z1 = lu.zp * (w.c + w.xp);
+    z2 = lu.zm * (w.zm + w.d1);
+    gu = fmad(cf.tcx, xu, fmad(cf.tcy, y, fmad(cf.t1kp, z1, -(cf.t2km * z2))));
 
     // ---- d L / d v(p)
-    g = zero;
-    // sv, +tcy v(c-y)(v(c)+v(c-y)): c = p+y (A and C), c = p (B)
-    t = tcy * (lv.yp * (v.yp + v.c) + lv.c * v.ym + lv.yp * v.c);
-    g += a1k ? t : zero;
-    // sv, -tcy v(c+y)(v(c)+v(c+y)): c = p-y (A and C), c = p (B)
-    t = tcy * (lv.ym * (v.ym + v.c) + lv.c * v.yp + lv.ym * v.c);
-    g -= a1k ? t : zero;
-    // sv, +tcx v(c-x)(u(c-x)+u(c-x+y)): A at p, c = p+x
-    t = tcx * (lv.xp * (u.c + u.yp));
-    g += a1k ? t : zero;
-    // sv, -tcx v(c+x)(u(c)+u(c+y)): A at p, c = p-x
-    t = tcx * (lv.xm * (u.xm + u.d1));
-    g -= a1k ? t : zero;
-    // sv, +tzc1 v(c-z)(w(c-z)+w(c+y-z)): A at p, c = p+z
-    t = cf.t1kp * (lv.zp * (w.c + w.yp));
-    g += a1kp ? t : zero;
-    // sv, -tzc2 v(c+z)(w(c)+w(c+y)): A at p, c = p-z
-    t = cf.t2km * (lv.zm * (w.zm + w.d2));
-    g -= a2km ? t : zero;
-    // su, +tcy u(c-y)(v(c-y)+v(c+x-y)): B at p (c = p+y), C at p (c = p-x+y)
-    t = tcy * (lu.yp * u.c + lu.d1 * u.xm);
-    g += a1k ? t : zero;
-    // su, -tcy u(c+y)(v(c)+v(c+x)): B at p (c = p), C at p (c = p-x)
-    t = tcy * (lu.c * u.yp + lu.xm * u.d1);
-    g -= a1k ? t : zero;
-    // sw, +tcy w(c-y)(v(c-y)+v(c-y+z)): B at p (c = p+y), C at p (c = p+y-z)
-    t = tcy * (a2k ? lw.yp * w.c : zero) + tcy * (a2km ? lw.d2 * w.zm : zero);
-    g += t;
-    // sw, -tcy w(c+y)(v(c)+v(c+z)): B at p (c = p), C at p (c = p-z)
-    t = tcy * (a2k ? lw.c * w.yp : zero) + tcy * (a2km ? lw.zm * w.d2 : zero);
-    g -= t;
-    gv = g;
+    // tcy: sv y term (A, C at c = p+y; B at c = p) minus its mirror at p-y,
+    //      su y terms (B at c = p+y / p; C at c = p-x+y / p-x),
+    //      sw y terms (B at c = p+y / p; C at c = p+y-z / p-z)
+    x = lv.yp * fmad(two, v.c, v.yp);
+    x = fmad(lv.c, v.ym, x);
+    x = fmad(-lv.ym, fmad(two, v.c, v.ym), x);
+    x = fmad(-lv.c, v.yp, x);
+    y = lu.yp * u.c;
+    y = fmad(lu.d1, u.xm, y);
+    y = fmad(-lu.c, u.yp, y);
+    y = fmad(-lu.xm, u.d1, y);
+    z1 = lw.yp * w.c;
+    z1 = fmad(lw.d2, w.zm, z1);
+    z1 = fmad(-lw.c, w.yp, z1);
+    z1 = fmad(-lw.zm, w.d2, z1);
+    const T yv = (x + y) + z1;
+    // tcx: sv x terms, A at c = p+x and c = p-x
+    x = lv.xp * (u.c + u.yp);
+    x = fmad(-lv.xm, u.xm + u.d1, x);
+    // tzc1[k+1]: sv z term, A at c = p+z;  tzc2[k-1]: A at c = p-z
+    z1 = lv.zp * (w.c + w.yp);
+    z2 = lv.zm * (w.zm + w.d2);
+    gv = fmad(cf.tcy, yv, fmad(cf.tcx, x, fmad(cf.t1kp, z1, -(cf.t2km * z2))));
 
     // ---- d L / d w(p)
-    g = zero;
-    // su, +tzc1 u(c-z)(w(c-z)+w(c+x-z)): B at p (c = p+z), C at p (c = p-x+z)
-    t = cf.t1kp * (lu.zp * u.c + lu.d2 * u.xm);
-    g += a1kp ? t : zero;
-    // su, -tzc2 u(c+z)(w(c)+w(c+x)): B at p (c = p), C at p (c = p-x)
-    t = cf.t2k * (lu.c * u.zp + lu.xm * u.d2);
-    g -= a2k ? t : zero;
-    // sv, +tzc1 v(c-z)(w(c-z)+w(c+y-z)): B at p (c = p+z), C at p (c = p-y+z)
-    t = cf.t1kp * (lv.zp * v.c + lv.d2 * v.ym);
-    g += a1kp ? t : zero;
-    // sv, -tzc2 v(c+z)(w(c)+w(c+y)): B at p (c = p), C at p (c = p-y)
-    t = cf.t2k * (lv.c * v.zp + lv.ym * v.d2);
-    g -= a2k ? t : zero;
-    // sw, +tcx w(c-x)(u(c-x)+u(c-x+z)): A at p, c = p+x
-    t = tcx * (lw.xp * (u.c + u.zp));
-    g += a2k ? t : zero;
-    // sw, -tcx w(c+x)(u(c)+u(c+z)): A at p, c = p-x
-    t = tcx * (lw.xm * (u.xm + u.d2));
-    g -= a2k ? t : zero;
-    // sw, +tcy w(c-y)(v(c-y)+v(c-y+z)): A at p, c = p+y
-    t = tcy * (lw.yp * (v.c + v.zp));
-    g += a2k ? t : zero;
-    // sw, -tcy w(c+y)(v(c)+v(c+z)): A at p, c = p-y
-    t = tcy * (lw.ym * (v.ym + v.d2));
-    g -= a2k ? t : zero;
-    // sw, +tzc1 w(c-z)(w(c)+w(c-z)): A and C at p (c = p+z), B at p (c = p)
-    t = cf.t1kp * (lw.zp * (w.zp + w.c) + lw.zp * w.c);
-    g += a2kp ? t : zero;
-    t = cf.t1k * (lw.c * w.zm);
-    g += a2k ? t : zero;
-    // sw, -tzc2 w(c+z)(w(c)+w(c+z)): A and C at p (c = p-z), B at p (c = p)
-    t = cf.t2km * (lw.zm * (w.zm + w.c) + lw.zm * w.c);
-    g -= a2km ? t : zero;
-    t = cf.t2k * (lw.c * w.zp);
-    g -= a2k ? t : zero;
-    gw = g;
+    // tzc1[k+1]: su, sv z terms (B at c = p+z; C at c = p-x+z / p-y+z),
+    //            sw z term (A, C at c = p+z)
+    z1 = lu.zp * u.c;
+    z1 = fmad(lu.d2, u.xm, z1);
+    x = lv.zp * v.c;
+    x = fmad(lv.d2, v.ym, x);
+    z1 = fmad(lw.zp, fmad(two, w.c, w.zp), z1) + x;
+    // tzc2[k]: su, sv z terms (B at c = p; C at c = p-x / p-y), sw z term (B at c = p)
+    z2 = lu.c * u.zp;
+    z2 = fmad(lu.xm, u.d2, z2);
+    y = lv.c * v.zp;
+    y = fmad(lv.ym, v.d2, y);
+    z2 = fmad(lw.c, w.zp, z2) + y;
+    // tcx, tcy: sw x and y terms, A at c = p+x / p-x and p+y / p-y
+    x = lw.xp * (u.c + u.zp);
+    x = fmad(-lw.xm, u.xm + u.d2, x);
+    y = lw.yp * (v.c + v.zp);
+    y = fmad(-lw.ym, v.ym + v.d2, y);
+    // tzc1[k]: sw z term, B at c = p;  tzc2[k-1]: sw z term, A and C at c = p-z
+    T g = fmad(cf.t1kp, z1, -(t2k * z2));
+    g = fmad(cf.tcx, x, g);
+    g = fmad(cf.tcy, y, g);
+    g = fmad(cf.t1k, lw.c * w.zm, g);
+    gw = fmad(-cf.t2km, lw.zm * fmad(two, w.c, w.zm), g);
 }
