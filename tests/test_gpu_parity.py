@@ -225,3 +225,35 @@ def test_every_march_variant_matches_direct(pw, variant, dtype):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
     for x, y in zip(ref_a[3:], got_g):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("halo", [1, 3, 5])
+@pytest.mark.parametrize("shape", [(9, 10, 64, 21), (5, 4, 7, 22)], ids=lambda s: "x".join(map(str, s[:3])))
+def test_other_halo_widths(pw, kernel, halo, shape):
+    """Storage with halo 1, 3 and 5 (the scheme reads only the first halo
+    layer; the rest is layout): forward bitwise, adjoint within 1e-12."""
+    nx, ny, nz, seed = shape
+    if not march_runs(pw, nz, kernel):
+        pytest.skip("x-marching kernel is specialised for nz == 64")
+    log("halo %d %s %s" % (halo, kernel, shape))
+    fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 5)
+    tzc1, tzc2, tcx, tcy = coef
+    st_h = [oracle.pad_periodic(a, halo) for a in fields]
+    sl_h = [oracle.pad_periodic(a, halo) for a in lams]
+    ref_s = oracle.fwd(*st_h, *coef, halo)
+    ref_g = oracle.adj(*st_h, *sl_h, *coef, halo)
+    st = [pw.pad_periodic(t, halo) for t in to_dev(fields, torch.float64)]
+    sl = [pw.pad_periodic(t, halo) for t in to_dev(lams, torch.float64)]
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    prev = pw.set_kernel(kernel)
+    try:
+        out = pw.fwd_adj(*st, *sl, t1, t2, tcx, tcy, halo)
+    finally:
+        pw.set_kernel(prev)
+    torch.cuda.synchronize()
+    inner_h = lambda a: a[halo:-halo, halo:-halo, halo:-halo]
+    for got, ref in zip(out[:3], ref_s):
+        assert np.array_equal(inner_h(got.cpu().numpy()), inner_h(ref))
+    for got, ref in zip(out[3:], ref_g):
+        assert normwise(inner_h(got.cpu().numpy()), inner_h(ref)) <= 1e-12
