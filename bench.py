@@ -9,11 +9,16 @@ advection kernel.
 
 Printed: one JSON line with the headline value (FP64 fused fwd+adj Gcells/s),
 the roofline of that kernel (algorithmic bytes / measured average launch time
-against 8 TB/s HBM), per-path figures (fwd / adj / fused in FP64 and FP32),
+against 8 TB/s HBM), per-path figures (fwd / adj / fused in FP64, FP32, and
+FP32 storage with FP64 arithmetic),
 and the CPU oracle timed on a bounded sample of the same workload.
 
+Also printed, as context: the host-resident offload (fields in pinned host
+memory, pipelined x-slab transfers, pw_advect_fwd_host) at 4096x1024x64.
+
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
-       [--kernel auto|direct|march] [--no-cpu-baseline] [--paths-reps R]
+       [--kernel auto|direct|march] [--no-cpu-baseline] [--no-offload]
+       [--paths-reps R]
 """
 import argparse
 import hashlib
@@ -61,8 +66,9 @@ def measured_traffic(kernel_name, workload):
 
 
 class Grid:
-    def __init__(self, pw, torch, nx, ny, nz, h, dtype, seed, with_lambda):
+    def __init__(self, pw, torch, nx, ny, nz, h, dtype, seed, with_lambda, compute=None):
         self.nx, self.ny, self.nz, self.h = nx, ny, nz, h
+        self.compute = compute
         self.cells = nx * ny * nz
         shape = (nx + 2 * h, ny + 2 * h, nz + 2 * h)
         dev = torch.device("cuda:0")
@@ -85,13 +91,14 @@ class Grid:
         self.t2 = torch.from_numpy(tzc2).to(dev)
 
     def launch(self, pw, path):
+        c = self.compute
         if path == "fwd":
-            pw.fwd(*self.f, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.s)
+            pw.fwd(*self.f, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.s, compute=c)
         elif path == "adj":
-            pw.adj(*self.f, *self.l, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.g)
+            pw.adj(*self.f, *self.l, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.g, compute=c)
         else:
             pw.fwd_adj(*self.f, *self.l, self.t1, self.t2, self.tcx, self.tcy, self.h,
-                       out=self.s + self.g)
+                       out=self.s + self.g, compute=c)
 
 
 def time_launches(torch, fn, reps):
@@ -167,6 +174,56 @@ def cpu_baseline(nx, ny, nz, seed, budget_s=12.0, planes=32):
     }
 
 
+def offload_measure(pw, torch, reps=3, chunk=64):
+    """Host-resident fields (pinned) at the paper's largest grid, 2^28 cells:
+    pipelined pw_advect_fwd_host against its parts measured alone."""
+    from paper_2010_01545_amd import inputs
+    nx, ny, nz, h, seed = 4096, 1024, 64, 2, 4
+    cells = nx * ny * nz
+    dt = torch.float64
+    shape = (nx + 2 * h, ny + 2 * h, nz + 2 * h)
+    dev = torch.device("cuda:0")
+    g = Grid(pw, torch, nx, ny, nz, h, dt, seed, False)        # device copies of the winds
+    host_in = [torch.empty(shape, dtype=dt, pin_memory=True) for _ in range(3)]
+    host_out = [torch.empty(shape, dtype=dt, pin_memory=True) for _ in range(3)]
+    for hsrc, d in zip(host_in, g.f):
+        hsrc.copy_(d)
+    ws = torch.empty(pw.offload_workspace_bytes(shape, h, dt, chunk), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(n):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / n
+
+    run = lambda: pw.fwd_host(*host_in, g.t1, g.t2, g.tcx, g.tcy, h, *host_out, chunk, ws)
+    t_off = timed(run, reps)
+    t_h2d = timed(lambda: [d.copy_(hsrc, non_blocking=True) for d, hsrc in zip(g.f, host_in)], reps)
+    t_d2h = timed(lambda: [o.copy_(d, non_blocking=True) for o, d in zip(host_out, g.s)], reps)
+    t_k = timed(lambda: g.launch(pw, "fwd"), reps)
+    nbytes = 3 * shape[0] * shape[1] * shape[2] * 8
+    rec = {
+        "workload": "%dx%dx%d FP64 forward, fields and source terms in pinned host memory, halo %d, "
+                    "x-slabs of %d planes" % (nx, ny, nz, h, chunk),
+        "cells": cells,
+        "gcells_per_s_incl_transfers": cells / (t_off * 1e-3) / 1e9,
+        "ms_pipelined": t_off,
+        "ms_copy_in_alone": t_h2d, "ms_copy_out_alone": t_d2h, "ms_kernel_alone": t_k,
+        "copy_in_GBps": nbytes / (t_h2d * 1e-3) / 1e9, "copy_out_GBps": nbytes / (t_d2h * 1e-3) / 1e9,
+        "overlap": (t_h2d + t_d2h + t_k) / t_off,
+        "bytes_each_way": nbytes,
+    }
+    del g, host_in, host_out, ws
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +234,7 @@ def main():
     ap.add_argument("--paths-reps", type=int, default=10)
     ap.add_argument("--no-paths", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-offload", action="store_true")
     ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64")
     args = ap.parse_args()
 
@@ -211,7 +269,7 @@ def main():
     if args.only:
         path, dt = args.only.split(":")
         g = Grid(pw, torch, nx, ny, nz, h, torch.float64 if dt == "f64" else torch.float32, seed,
-                 path != "fwd")
+                 path != "fwd", compute=torch.float64 if dt == "f32f64" else None)
         torch.cuda.synchronize()
         for _ in range(args.warmup + args.steps):
             g.launch(pw, path)
@@ -251,8 +309,18 @@ def main():
             log("bench: %s f32 %.2f ms" % (p, paths[p + "_f32"]["ms_avg"]))
         del g
         torch.cuda.empty_cache()
-        for p in ("fwd", "fused"):
-            paths[p + "_f32"]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + "_f32"]["ms_avg"]
+        # FP32 storage with FP64 arithmetic
+        g = Grid(pw, torch, nx, ny, nz, h, torch.float32, seed, True, compute=torch.float64)
+        for p in ("fwd", "adj", "fused"):
+            g.launch(pw, p)
+            paths[p + "_f32f64"] = path_record(p, 4, cells, time_launches(torch, lambda: g.launch(pw, p),
+                                                                          args.paths_reps))
+            log("bench: %s f32-storage/f64-arithmetic %.2f ms" % (p, paths[p + "_f32f64"]["ms_avg"]))
+        del g
+        torch.cuda.empty_cache()
+        for p in ("fwd", "adj", "fused"):
+            for v in ("_f32", "_f32f64"):
+                paths[p + v]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + v]["ms_avg"]
 
     kname = "fused_f64"
     traffic = measured_traffic(kname, args.workload)
@@ -276,6 +344,12 @@ def main():
         "paths": paths,
         "source_hash": kernel_source_hash(),
     }
+    if not args.no_offload:
+        log("bench: host-resident offload at 4096x1024x64")
+        out["offload"] = offload_measure(pw, torch)
+        log("bench: offload %.1f ms pipelined (in %.1f, kernel %.1f, out %.1f)" % (
+            out["offload"]["ms_pipelined"], out["offload"]["ms_copy_in_alone"],
+            out["offload"]["ms_kernel_alone"], out["offload"]["ms_copy_out_alone"]))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, seed)

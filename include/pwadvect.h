@@ -15,15 +15,16 @@
  * contiguous (section 3, Listings 3 and 4).  Interior cell (i, j, k) with
  * 0 <= i < nx, 0 <= j < ny, 0 <= k < nz is element
  *     ((i + halo) * (ny + 2*halo) + (j + halo)) * (nz + 2*halo) + (k + halo).
- * Element type: double for PW_F64, float for PW_F32.
+ * Element type: double for PW_F64, float for PW_F32 and PW_F32_F64.
  * tzc1, tzc2 are double arrays of length nz indexed by interior level k, for
- * both element types (the FP32 path rounds them to float where it uses them).
- * tcx, tcy are passed by value as double (rounded to float by PW_F32).
+ * every dtype (PW_F32 rounds them to float where it uses them).
+ * tcx, tcy are passed by value as double (rounded to float by PW_F32 only).
  *
  * Every pointer is a device pointer (hipMalloc / torch device memory) owned by
- * the caller.  The library allocates no device memory, keeps no state between
- * calls other than the kernel selection and the last error text, and is
- * thread-safe apart from pw_set_kernel.
+ * the caller, except the host field arrays of pw_advect_fwd_host.  The library
+ * allocates no memory; it keeps the kernel selection, the last error text and,
+ * once pw_advect_fwd_host has run on a device, two copy streams and a few
+ * events for that device.  It is thread-safe apart from pw_set_kernel.
  *
  * ---------------------------------------------------------------- semantics
  * Levels follow Listing 1: Fortran k = 2..z_size is interior k = 1..nz-1.
@@ -61,11 +62,18 @@
 #ifndef PWADVECT_H
 #define PWADVECT_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
 
-typedef enum { PW_F64 = 0, PW_F32 = 1 } pw_dtype;
+/* Element type of the field arrays and arithmetic type of the scheme.
+ * PW_F32_F64 stores fields as float but computes in double (operands are
+ * widened exactly, each result is rounded to float once); it moves the bytes
+ * of PW_F32 with the arithmetic of PW_F64.  The utility calls treat it as
+ * float storage. */
+typedef enum { PW_F64 = 0, PW_F32 = 1, PW_F32_F64 = 2 } pw_dtype;
 
 enum {
     PW_OK = 0,
@@ -119,6 +127,35 @@ int pw_advect_fwd_adj(const void *u, const void *v, const void *w,
                       int nx, int ny, int nz, int halo,
                       void *su, void *sv, void *sw, void *gu, void *gv, void *gw,
                       int dtype, void *stream);
+
+/*
+ * Forward source terms for fields held in HOST memory: the offload measured in
+ * the paper's sections 4 and 5 (winds copied to the accelerator, kernel, source
+ * terms copied back), with the transfer cut into x-slabs of `chunk` planes and
+ * pipelined as its section 6 proposes: the copy in of one slab, the kernel on
+ * the previous slab and the copy out of the one before run concurrently.
+ *   u, v, w     host storage arrays (layout above, x/y halos filled);
+ *   su, sv, sw  host storage arrays; interior columns are written (interior
+ *               levels and zero z halo), x/y halo columns are not;
+ *   tzc1, tzc2  DEVICE arrays of nz doubles;
+ *   workspace   DEVICE memory of at least pw_offload_workspace_bytes(...)
+ *               bytes (three slab buffer sets), owned by the caller.
+ * Host arrays should be pinned (hipHostMalloc) for the copies to run
+ * asynchronously; pageable memory works but the copies then block the host.
+ * The call is asynchronous on `stream`: it starts after the work already queued
+ * there, and work queued there afterwards sees every result.  Kernels run on
+ * `stream`; the copies use two streams the library creates once per device and
+ * keeps until the process ends (default priority).  Concurrent calls are
+ * serialized while they are queued.  Results are identical to pw_advect_fwd on
+ * the same data.  Errors as for pw_advect_fwd; PW_ERR_SIZE if the workspace is
+ * too small.
+ */
+size_t pw_offload_workspace_bytes(int nx, int ny, int nz, int halo, int dtype, int chunk);
+int pw_advect_fwd_host(const void *u, const void *v, const void *w,
+                       const double *tzc1, const double *tzc2, double tcx, double tcy,
+                       int nx, int ny, int nz, int halo,
+                       void *su, void *sv, void *sw,
+                       int chunk, void *workspace, size_t workspace_bytes, int dtype, void *stream);
 
 /*
  * Periodic halo fill in place (the halo swap that precedes advection in each

@@ -32,12 +32,14 @@ int ok()
 }
 
 size_t elem_size(int dtype) { return dtype == PW_F64 ? 8 : 4; }
+bool storage_is_double(int dtype) { return dtype == PW_F64; }
 
 // Shape checks shared by every entry point; fills g and the byte count of
 // one storage array.
 int check_shape(int nx, int ny, int nz, int halo, int dtype, Geom& g, size_t& bytes)
 {
-    if (dtype != PW_F64 && dtype != PW_F32) return fail(PW_ERR_ARG, "unknown dtype %d", dtype);
+    if (dtype != PW_F64 && dtype != PW_F32 && dtype != PW_F32_F64)
+        return fail(PW_ERR_ARG, "unknown dtype %d", dtype);
     if (nx < 1 || ny < 1) return fail(PW_ERR_ARG, "nx=%d, ny=%d: need nx >= 1 and ny >= 1", nx, ny);
     if (nz < 2) return fail(PW_ERR_ARG, "nz=%d: need nz >= 2", nz);
     if (halo < 1) return fail(PW_ERR_ARG, "halo=%d: need halo >= 1", halo);
@@ -139,7 +141,7 @@ int resolve_kernel(const Geom& g, const Arr* arrs, int n)
     return march ? PW_KERNEL_MARCH : PW_KERNEL_DIRECT;
 }
 
-template <typename T>
+template <typename T, typename C>
 int do_fwd(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
            double tcx, double tcy, const Geom& g, size_t bytes, void* su, void* sv, void* sw,
            hipStream_t stream)
@@ -155,16 +157,16 @@ int do_fwd(const void* u, const void* v, const void* w, const double* tzc1, cons
     const Arr fields[6] = {in[0], in[1], in[2], out[0], out[1], out[2]};
     const int kern = resolve_kernel<T>(g, fields, 6);
     if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64 and 16-byte aligned arrays");
-    FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, (T)tcx, (T)tcy, (T*)su, (T*)sv, (T*)sw};
+    FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw};
     (void)hipGetLastError();
     if (kern == PW_KERNEL_MARCH)
-        launch_fwd_march<T>(a, g, stream);
+        launch_fwd_march<T, C>(a, g, stream);
     else
-        launch_fwd_direct<T>(a, g, stream);
+        launch_fwd_direct<T, C>(a, g, stream);
     return launched("pw_advect_fwd");
 }
 
-template <typename T>
+template <typename T, typename C>
 int do_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv, const void* lw,
            const double* tzc1, const double* tzc2, double tcx, double tcy, const Geom& g, size_t bytes,
            void* su, void* sv, void* sw, void* gu, void* gv, void* gw, hipStream_t stream)
@@ -199,12 +201,12 @@ int do_adj(const void* u, const void* v, const void* w, const void* lu, const vo
     const int kern = resolve_kernel<T>(g, fields, nf);
     if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64 and 16-byte aligned arrays");
     AdjArgs<T> a{(const T*)u, (const T*)v, (const T*)w, (const T*)lu, (const T*)lv, (const T*)lw,
-                 tzc1, tzc2, (T)tcx, (T)tcy, (T*)su, (T*)sv, (T*)sw, (T*)gu, (T*)gv, (T*)gw};
+                 tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw, (T*)gu, (T*)gv, (T*)gw};
     (void)hipGetLastError();
     if (kern == PW_KERNEL_MARCH)
-        launch_adj_march<T>(a, g, stream);
+        launch_adj_march<T, C>(a, g, stream);
     else
-        launch_adj_direct<T>(a, g, stream);
+        launch_adj_direct<T, C>(a, g, stream);
     return launched(fused ? "pw_advect_fwd_adj" : "pw_advect_adj");
 }
 
@@ -229,8 +231,10 @@ int pw_advect_fwd(const void* u, const void* v, const void* w, const double* tzc
     int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
     if (rc) return rc;
     if (dtype == PW_F64)
-        return do_fwd<double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
-    return do_fwd<float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+        return do_fwd<double, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+    if (dtype == PW_F32_F64)
+        return do_fwd<float, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+    return do_fwd<float, float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
 }
 
 int pw_advect_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
@@ -243,10 +247,13 @@ int pw_advect_adj(const void* u, const void* v, const void* w, const void* lu, c
     if (rc) return rc;
     if (!gu || !gv || !gw) return fail(PW_ERR_ARG, "gu, gv, gw must not be NULL");
     if (dtype == PW_F64)
-        return do_adj<double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr,
-                              nullptr, gu, gv, gw, (hipStream_t)stream);
-    return do_adj<float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr, nullptr,
-                         gu, gv, gw, (hipStream_t)stream);
+        return do_adj<double, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr,
+                                      nullptr, gu, gv, gw, (hipStream_t)stream);
+    if (dtype == PW_F32_F64)
+        return do_adj<float, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr,
+                                     nullptr, gu, gv, gw, (hipStream_t)stream);
+    return do_adj<float, float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr, nullptr,
+                                gu, gv, gw, (hipStream_t)stream);
 }
 
 int pw_advect_fwd_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
@@ -261,10 +268,74 @@ int pw_advect_fwd_adj(const void* u, const void* v, const void* w, const void* l
     if (!su || !sv || !sw) return fail(PW_ERR_ARG, "su, sv, sw must not be NULL");
     if (!gu || !gv || !gw) return fail(PW_ERR_ARG, "gu, gv, gw must not be NULL");
     if (dtype == PW_F64)
-        return do_adj<double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv, gw,
-                              (hipStream_t)stream);
-    return do_adj<float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv, gw,
-                         (hipStream_t)stream);
+        return do_adj<double, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv,
+                                      gw, (hipStream_t)stream);
+    if (dtype == PW_F32_F64)
+        return do_adj<float, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv,
+                                     gw, (hipStream_t)stream);
+    return do_adj<float, float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv, gw,
+                                (hipStream_t)stream);
+}
+
+size_t pw_offload_workspace_bytes(int nx, int ny, int nz, int halo, int dtype, int chunk)
+{
+    Geom g;
+    size_t bytes;
+    if (check_shape(nx, ny, nz, halo, dtype, g, bytes)) return 0;
+    if (chunk < 1) return 0;
+    if (chunk > nx) chunk = nx;
+    return offload_workspace_bytes(g, chunk, elem_size(dtype));
+}
+
+int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
+                       double tcx, double tcy, int nx, int ny, int nz, int halo, void* su, void* sv, void* sw,
+                       int chunk, void* workspace, size_t workspace_bytes, int dtype, void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    if (chunk < 1) return fail(PW_ERR_ARG, "chunk=%d: need chunk >= 1", chunk);
+    if (chunk > nx) chunk = nx;
+    const size_t es = elem_size(dtype);
+    const size_t need = offload_workspace_bytes(g, chunk, es);
+    if (!workspace) return fail(PW_ERR_ARG, "workspace is NULL");
+    if (workspace_bytes < need)
+        return fail(PW_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
+                    need);
+    const Arr in[3] = {{u, bytes, es, "u"}, {v, bytes, es, "v"}, {w, bytes, es, "w"}};
+    const Arr out[3] = {{su, bytes, es, "su"}, {sv, bytes, es, "sv"}, {sw, bytes, es, "sw"}};
+    rc = check_host_side(in, 3, out, 3);
+    if (rc) return rc;
+    const Arr dev[3] = {{tzc1, (size_t)nz * 8, 8, "tzc1"}, {tzc2, (size_t)nz * 8, 8, "tzc2"},
+                        {workspace, need, 16, "workspace"}};
+    rc = check_host_side(dev, 3, nullptr, 0);
+    if (rc) return rc;
+    rc = check_device(dev, 3);
+    if (rc) return rc;
+    // the slab kernels follow the same selection as pw_advect_fwd
+    Geom sg = g;
+    sg.nx = chunk;
+    const Arr ws[1] = {{workspace, need, 16, "workspace"}};
+    const int kern = storage_is_double(dtype) ? resolve_kernel<double>(sg, ws, 1) : resolve_kernel<float>(sg, ws, 1);
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64");
+    const char* what = "";
+    int e;
+    const bool march = kern == PW_KERNEL_MARCH;
+    if (dtype == PW_F64)
+        e = offload_fwd<double, double>((const double*)u, (const double*)v, (const double*)w, tzc1, tzc2, tcx,
+                                        tcy, g, (double*)su, (double*)sv, (double*)sw, chunk, workspace, march,
+                                        (hipStream_t)stream, &what);
+    else if (dtype == PW_F32_F64)
+        e = offload_fwd<float, double>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx, tcy,
+                                       g, (float*)su, (float*)sv, (float*)sw, chunk, workspace, march,
+                                       (hipStream_t)stream, &what);
+    else
+        e = offload_fwd<float, float>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx, tcy, g,
+                                      (float*)su, (float*)sv, (float*)sw, chunk, workspace, march,
+                                      (hipStream_t)stream, &what);
+    if (e) return fail(PW_ERR_HIP, "pw_advect_fwd_host: %s: %s", what, hipGetErrorString((hipError_t)e));
+    return launched("pw_advect_fwd_host");
 }
 
 int pw_halo_periodic(void* storage, int nx, int ny, int nz, int halo, int dtype, void* stream)
@@ -276,7 +347,7 @@ int pw_halo_periodic(void* storage, int nx, int ny, int nz, int halo, int dtype,
     rc = check_one(storage, bytes, elem_size(dtype), "storage");
     if (rc) return rc;
     (void)hipGetLastError();
-    if (dtype == PW_F64)
+    if (storage_is_double(dtype))
         launch_halo_periodic<double>((double*)storage, g, (hipStream_t)stream);
     else
         launch_halo_periodic<float>((float*)storage, g, (hipStream_t)stream);
@@ -299,7 +370,7 @@ int pw_pad_periodic(const void* interior, void* storage, int nx, int ny, int nz,
     rc = check_device(all, 2);
     if (rc) return rc;
     (void)hipGetLastError();
-    if (dtype == PW_F64)
+    if (storage_is_double(dtype))
         launch_pad_periodic<double>((const double*)interior, (double*)storage, g, (hipStream_t)stream);
     else
         launch_pad_periodic<float>((const float*)interior, (float*)storage, g, (hipStream_t)stream);
@@ -317,7 +388,7 @@ int pw_fill_uniform(void* storage, int nx, int ny, int nz, int halo, unsigned lo
     rc = check_one(storage, bytes, elem_size(dtype), "storage");
     if (rc) return rc;
     (void)hipGetLastError();
-    if (dtype == PW_F64)
+    if (storage_is_double(dtype))
         launch_fill_uniform<double>((double*)storage, g, seed, field_id, amp, zero_lids, (hipStream_t)stream);
     else
         launch_fill_uniform<float>((float*)storage, g, seed, field_id, amp, zero_lids, (hipStream_t)stream);

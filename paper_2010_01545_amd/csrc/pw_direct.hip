@@ -50,7 +50,13 @@ __device__ __forceinline__ Star<T> load_star(const T* __restrict__ f, long long 
     return s;
 }
 
-template <typename T>
+template <typename C, typename T>
+__device__ __forceinline__ Star<C> widen(const Star<T>& s)
+{
+    return Star<C>{(C)s.c, (C)s.xm, (C)s.xp, (C)s.ym, (C)s.yp, (C)s.zm, (C)s.zp, (C)s.d1, (C)s.d2};
+}
+
+template <typename T, typename C>
 __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -66,19 +72,19 @@ __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g
             a.sw[b] = T(0);
             continue;
         }
-        const Star<T> u = load_star<T, 0, false>(a.u, b, g.sx, g.sy, k, g.nz);
-        const Star<T> v = load_star<T, 1, false>(a.v, b, g.sx, g.sy, k, g.nz);
-        const Star<T> w = load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz);
-        const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, k, g.nz);
-        T su, sv, sw;
+        const Star<C> u = widen<C>(load_star<T, 0, false>(a.u, b, g.sx, g.sy, k, g.nz));
+        const Star<C> v = widen<C>(load_star<T, 1, false>(a.v, b, g.sx, g.sy, k, g.nz));
+        const Star<C> w = widen<C>(load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz));
+        const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, k, g.nz);
+        C su, sv, sw;
         pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
-        a.su[b] = su;
-        a.sv[b] = sv;
-        a.sw[b] = sw;
+        a.su[b] = (T)su;
+        a.sv[b] = (T)sv;
+        a.sw[b] = (T)sw;
     }
 }
 
-template <typename T, bool FUSED>
+template <typename T, typename C, bool FUSED>
 __global__ void __launch_bounds__(kBlock) adj_direct_kernel(AdjArgs<T> a, Geom g)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -99,25 +105,25 @@ __global__ void __launch_bounds__(kBlock) adj_direct_kernel(AdjArgs<T> a, Geom g
             a.gw[b] = T(0);
             continue;
         }
-        const Star<T> u = load_star<T, 0, false>(a.u, b, g.sx, g.sy, k, g.nz);
-        const Star<T> v = load_star<T, 1, false>(a.v, b, g.sx, g.sy, k, g.nz);
-        const Star<T> w = load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz);
-        const Star<T> lu = load_star<T, 0, true>(a.lu, b, g.sx, g.sy, k, g.nz);
-        const Star<T> lv = load_star<T, 1, true>(a.lv, b, g.sx, g.sy, k, g.nz);
-        const Star<T> lw = load_star<T, 2, true>(a.lw, b, g.sx, g.sy, k, g.nz);
-        const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, k, g.nz);
+        const Star<C> u = widen<C>(load_star<T, 0, false>(a.u, b, g.sx, g.sy, k, g.nz));
+        const Star<C> v = widen<C>(load_star<T, 1, false>(a.v, b, g.sx, g.sy, k, g.nz));
+        const Star<C> w = widen<C>(load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz));
+        const Star<C> lu = widen<C>(load_star<T, 0, true>(a.lu, b, g.sx, g.sy, k, g.nz));
+        const Star<C> lv = widen<C>(load_star<T, 1, true>(a.lv, b, g.sx, g.sy, k, g.nz));
+        const Star<C> lw = widen<C>(load_star<T, 2, true>(a.lw, b, g.sx, g.sy, k, g.nz));
+        const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, k, g.nz);
         if (FUSED) {
-            T su, sv, sw;
+            C su, sv, sw;
             pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
-            a.su[b] = su;
-            a.sv[b] = sv;
-            a.sw[b] = sw;
+            a.su[b] = (T)su;
+            a.sv[b] = (T)sv;
+            a.sw[b] = (T)sw;
         }
-        T gu, gv, gw;
+        C gu, gv, gw;
         pw_adj_cell(u, v, w, lu, lv, lw, cf, k, g.nz, gu, gv, gw);
-        a.gu[b] = gu;
-        a.gv[b] = gv;
-        a.gw[b] = gw;
+        a.gu[b] = (T)gu;
+        a.gv[b] = (T)gv;
+        a.gw[b] = (T)gw;
     }
 }
 
@@ -131,22 +137,24 @@ inline dim3 direct_grid(const Geom& g)
 
 }  // namespace
 
-template <typename T>
+template <typename T, typename C>
 void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
 {
-    hipLaunchKernelGGL(fwd_direct_kernel<T>, direct_grid(g), dim3(kBlock), 0, s, a, g);
+    hipLaunchKernelGGL((fwd_direct_kernel<T, C>), direct_grid(g), dim3(kBlock), 0, s, a, g);
 }
 
-template <typename T>
+template <typename T, typename C>
 void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
 {
     if (a.su)
-        hipLaunchKernelGGL((adj_direct_kernel<T, true>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+        hipLaunchKernelGGL((adj_direct_kernel<T, C, true>), direct_grid(g), dim3(kBlock), 0, s, a, g);
     else
-        hipLaunchKernelGGL((adj_direct_kernel<T, false>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+        hipLaunchKernelGGL((adj_direct_kernel<T, C, false>), direct_grid(g), dim3(kBlock), 0, s, a, g);
 }
 
-template void launch_fwd_direct<double>(const FwdArgs<double>&, const Geom&, hipStream_t);
-template void launch_fwd_direct<float>(const FwdArgs<float>&, const Geom&, hipStream_t);
-template void launch_adj_direct<double>(const AdjArgs<double>&, const Geom&, hipStream_t);
-template void launch_adj_direct<float>(const AdjArgs<float>&, const Geom&, hipStream_t);
+template void launch_fwd_direct<double, double>(const FwdArgs<double>&, const Geom&, hipStream_t);
+template void launch_fwd_direct<float, float>(const FwdArgs<float>&, const Geom&, hipStream_t);
+template void launch_fwd_direct<float, double>(const FwdArgs<float>&, const Geom&, hipStream_t);
+template void launch_adj_direct<double, double>(const AdjArgs<double>&, const Geom&, hipStream_t);
+template void launch_adj_direct<float, float>(const AdjArgs<float>&, const Geom&, hipStream_t);
+template void launch_adj_direct<float, double>(const AdjArgs<float>&, const Geom&, hipStream_t);

@@ -11,12 +11,14 @@ struct Geom {
     int sy;           // Sz
 };
 
-// Operand bundles passed to the kernel launchers.
+// Operand bundles passed to the kernel launchers.  T is the storage type;
+// the kernels are also templated on the arithmetic type C (C = T, or
+// T = float with C = double), and round tcx, tcy and the profiles to C.
 template <typename T>
 struct FwdArgs {
     const T *u, *v, *w;
     const double *tzc1, *tzc2;
-    T tcx, tcy;
+    double tcx, tcy;
     T *su, *sv, *sw;
 };
 
@@ -24,20 +26,20 @@ template <typename T>
 struct AdjArgs {
     const T *u, *v, *w, *lu, *lv, *lw;
     const double *tzc1, *tzc2;
-    T tcx, tcy;
+    double tcx, tcy;
     T *su, *sv, *sw;   // forward outputs (fused launch only; null otherwise)
     T *gu, *gv, *gw;
 };
 
 // Direct kernels: one thread per storage level of each interior column,
 // every operand read from global memory.  Any nz >= 2, any halo >= 1.
-template <typename T> void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
-template <typename T> void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T, typename C> void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T, typename C> void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
 
 // x-marching kernels (nz == 64, 16-byte aligned arrays).
 template <typename T> bool march_supported(const Geom& g);
-template <typename T> void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
-template <typename T> void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T, typename C> void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T, typename C> void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
 
 // Utilities.
 template <typename T> void launch_halo_periodic(T* st, const Geom& g, hipStream_t s);
@@ -45,3 +47,10 @@ template <typename T> void launch_pad_periodic(const T* in, T* st, const Geom& g
 template <typename T> void launch_fill_uniform(T* st, const Geom& g, unsigned long long seed,
                                                int field_id, double amp, int zero_lids,
                                                hipStream_t s);
+
+// Host-resident fields: chunked, pipelined forward (pw_offload.hip).
+size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es);
+template <typename T, typename C>
+int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
+                const Geom& g, T* su, T* sv, T* sw, int chunk, void* workspace, bool use_march,
+                hipStream_t stream, const char** what);

@@ -117,12 +117,13 @@ struct MarchArgs {
     T* gr[3];          // gu, gv, gw (or unused)
     const double* tzc1;
     const double* tzc2;
-    T tcx, tcy;
+    double tcx, tcy;
 };
 
-// TY: compute columns per workgroup (TY + 2 wavefronts); D: planes
-// prefetched beyond the current xp plane (D >= 2).
-template <typename T, int NF, bool WS, bool WG, int TY, int D>
+// T: storage type (registers, LDS and DPP shifts work in it); C: arithmetic
+// type (T, or double for float storage).  TY: compute columns per workgroup
+// (TY + 2 wavefronts); D: planes prefetched beyond the current xp plane (D >= 2).
+template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D>
 __global__ void __launch_bounds__(64 * (TY + 2))
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 {
@@ -194,7 +195,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
         else if (f % 3 == 1) carry[f] = mask(f, ld(f, i0, -1, stbytes)); // F(i0, j-1)
         else carry[f] = T(0);
     }
-    const LevelCoef<T> cf = level_coef<T>(a.tzc1, a.tzc2, a.tcx, a.tcy, lane, NZ);
+    const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, lane, NZ);
 
     {
 #pragma unroll
@@ -232,7 +233,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 if (f % 3 == 1) R[f][rq1] = mask(f, R[f][rq1]);
             }
 
-            T out[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+            C out[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
             if (comp) {  // arithmetic only: no memory access inside the branch
                 Star<T> st[NF];
 #pragma unroll
@@ -261,9 +262,15 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                         q.d2 = below(q.yp);      // F(p, j+1, k-1)
                     }
                 }
-                if (WS) pw_fwd_cell(st[0], st[1], st[2], cf, lane, NZ, out[0], out[1], out[2]);
+                Star<C> sc[NF];  // operands in the arithmetic type
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const Star<T>& q = st[f];
+                    sc[f] = Star<C>{(C)q.c, (C)q.xm, (C)q.xp, (C)q.ym, (C)q.yp, (C)q.zm, (C)q.zp, (C)q.d1, (C)q.d2};
+                }
+                if (WS) pw_fwd_cell(sc[0], sc[1], sc[2], cf, lane, NZ, out[0], out[1], out[2]);
                 if (WG)
-                    pw_adj_cell(st[0], st[1], st[2], st[NF - 3], st[NF - 2], st[NF - 1], cf, lane, NZ,
+                    pw_adj_cell(sc[0], sc[1], sc[2], sc[NF - 3], sc[NF - 2], sc[NF - 1], cf, lane, NZ,
                                 out[3], out[4], out[5]);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -278,7 +285,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 if ((q < 3 && !WS) || (q >= 3 && !WG)) continue;
                 T* const dst = q < 3 ? a.s[q] : a.gr[q - 3];
                 const rsrc_t r = column_rsrc(column(dst, p, 0), stbytes);
-                buf_store(out[q], r, voff);
+                buf_store((T)out[q], r, voff);
                 buf_store(T(0), r, vpad);
             }
 
@@ -330,15 +337,15 @@ constexpr int lds_bytes()
     return (int)sizeof(T) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
 }
 
-template <typename T, int NF, bool WS, bool WG, int TY, int D>
+template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D>
 void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
     if constexpr (lds_bytes<T, NF, TY>() <= 65536) {
         const Launch l = plan(g, TY);
-        hipLaunchKernelGGL((march_kernel<T, NF, WS, WG, TY, D>), dim3(l.grid), dim3(64 * (TY + 2)), 0, s, m,
+        hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D>), dim3(l.grid), dim3(64 * (TY + 2)), 0, s, m,
                            g, l.LX, l.nstrips, l.nblocks);
     } else {
-        go<T, NF, WS, WG, kTY[0], kD[0]>(m, g, s);
+        go<T, C, NF, WS, WG, kTY[0], kD[0]>(m, g, s);
     }
 }
 
@@ -347,25 +354,25 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 // wherever the LDS ring fits 64 KiB; the FP64 six-field kernels keep
 // 6-column strips.  Deeper prefetch (D = 4) measured no faster.
 // PW_MARCH_VARIANT=0..3 overrides the choice for sweeps.
-template <typename T, int NF>
+template <typename T, typename C, int NF>
 int default_variant()
 {
-    return (NF == 3 || sizeof(T) == 4) ? 2 : 0;
+    return (NF == 3 || (sizeof(T) == 4 && sizeof(C) == 4)) ? 2 : 0;
 }
 
-template <typename T, int NF, bool WS, bool WG>
+template <typename T, typename C, int NF, bool WS, bool WG>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
-    int v = default_variant<T, NF>();
+    int v = default_variant<T, C, NF>();
     if (const char* e = std::getenv("PW_MARCH_VARIANT")) {
         const int q = std::atoi(e);
         if (q >= 0 && q < kVariants) v = q;
     }
     switch (v) {
-    case 1: go<T, NF, WS, WG, kTY[1], kD[1]>(m, g, s); break;
-    case 2: go<T, NF, WS, WG, kTY[2], kD[2]>(m, g, s); break;
-    case 3: go<T, NF, WS, WG, kTY[3], kD[3]>(m, g, s); break;
-    default: go<T, NF, WS, WG, kTY[0], kD[0]>(m, g, s); break;
+    case 1: go<T, C, NF, WS, WG, kTY[1], kD[1]>(m, g, s); break;
+    case 2: go<T, C, NF, WS, WG, kTY[2], kD[2]>(m, g, s); break;
+    case 3: go<T, C, NF, WS, WG, kTY[3], kD[3]>(m, g, s); break;
+    default: go<T, C, NF, WS, WG, kTY[0], kD[0]>(m, g, s); break;
     }
 }
 
@@ -377,7 +384,7 @@ bool march_supported(const Geom& g)
     return g.nz == NZ && g.h <= 32;
 }
 
-template <typename T>
+template <typename T, typename C>
 void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
 {
     MarchArgs<T, 3> m;
@@ -392,10 +399,10 @@ void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
     m.tzc2 = a.tzc2;
     m.tcx = a.tcx;
     m.tcy = a.tcy;
-    dispatch<T, 3, true, false>(m, g, s);
+    dispatch<T, C, 3, true, false>(m, g, s);
 }
 
-template <typename T>
+template <typename T, typename C>
 void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
 {
     MarchArgs<T, 6> m;
@@ -416,14 +423,16 @@ void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
     m.tcx = a.tcx;
     m.tcy = a.tcy;
     if (a.su)
-        dispatch<T, 6, true, true>(m, g, s);
+        dispatch<T, C, 6, true, true>(m, g, s);
     else
-        dispatch<T, 6, false, true>(m, g, s);
+        dispatch<T, C, 6, false, true>(m, g, s);
 }
 
 template bool march_supported<double>(const Geom&);
 template bool march_supported<float>(const Geom&);
-template void launch_fwd_march<double>(const FwdArgs<double>&, const Geom&, hipStream_t);
-template void launch_fwd_march<float>(const FwdArgs<float>&, const Geom&, hipStream_t);
-template void launch_adj_march<double>(const AdjArgs<double>&, const Geom&, hipStream_t);
-template void launch_adj_march<float>(const AdjArgs<float>&, const Geom&, hipStream_t);
+template void launch_fwd_march<double, double>(const FwdArgs<double>&, const Geom&, hipStream_t);
+template void launch_fwd_march<float, float>(const FwdArgs<float>&, const Geom&, hipStream_t);
+template void launch_fwd_march<float, double>(const FwdArgs<float>&, const Geom&, hipStream_t);
+template void launch_adj_march<double, double>(const AdjArgs<double>&, const Geom&, hipStream_t);
+template void launch_adj_march<float, float>(const AdjArgs<float>&, const Geom&, hipStream_t);
+template void launch_adj_march<float, double>(const AdjArgs<float>&, const Geom&, hipStream_t);

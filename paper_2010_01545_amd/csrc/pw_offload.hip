@@ -1,0 +1,166 @@
+// pw_offload.hip -- forward source terms for fields held in host memory: the
+// offload that the paper measures in its sections 4 and 5 (copy the winds to
+// the accelerator, run the kernel, copy the source terms back), with the
+// transfer split into x-slabs and pipelined so that the host->device copy of
+// one slab, the kernel on the previous one and the device->host copy of the
+// one before overlap (the chunked transfer its section 6 proposes).
+//
+// Slab k covers interior planes [i0, i0 + c).  In the storage layout the
+// planes i0 - h .. i0 + c + h - 1 (interior plus the real neighbouring
+// planes as x halo) are one contiguous run per field, so each input slab is a
+// single copy into a device slab array of c + 2h planes.  The forward kernel
+// runs on that slab as a grid of c planes; it writes the interior columns of
+// its c planes, which go back with one 2-D copy per field (rows = planes, the
+// ny interior columns of a plane being contiguous), so the host arrays' x/y
+// halo columns are never written.
+//
+// Three slab buffers rotate: copies in on one internal stream, kernels on the
+// caller's stream, copies out on a second internal stream, ordered by events.
+// The internal streams and events are created once per device (default
+// priority) and kept for the life of the process.
+#include <mutex>
+
+#include "../../include/pwadvect.h"
+#include "pw_internal.h"
+
+namespace {
+
+constexpr int kBuffers = 3;
+
+struct DeviceQueues {
+    bool ready = false;
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t start = nullptr, done_in[kBuffers] = {}, done_kernel[kBuffers] = {}, done_out[kBuffers] = {},
+               end_out = nullptr;
+};
+
+std::mutex g_queues_mutex;
+std::mutex g_enqueue_mutex;
+DeviceQueues g_queues[64];
+
+hipError_t queues_for_current_device(DeviceQueues** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_queues_mutex);
+    DeviceQueues& q = g_queues[dev];
+    if (!q.ready) {
+        const unsigned ev = hipEventDisableTiming;
+        if ((e = hipStreamCreateWithFlags(&q.h2d, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipStreamCreateWithFlags(&q.d2h, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&q.start, ev)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&q.end_out, ev)) != hipSuccess) return e;
+        for (int b = 0; b < kBuffers; ++b) {
+            if ((e = hipEventCreateWithFlags(&q.done_in[b], ev)) != hipSuccess) return e;
+            if ((e = hipEventCreateWithFlags(&q.done_kernel[b], ev)) != hipSuccess) return e;
+            if ((e = hipEventCreateWithFlags(&q.done_out[b], ev)) != hipSuccess) return e;
+        }
+        q.ready = true;
+    }
+    *out = &q;
+    return hipSuccess;
+}
+
+}  // namespace
+
+// Bytes of one slab buffer set: three input and three output slab arrays of
+// chunk + 2h planes each.
+size_t offload_slab_set_bytes(const Geom& g, int chunk, size_t es)
+{
+    return (size_t)6 * (size_t)(chunk + 2 * g.h) * (size_t)g.sx * es;
+}
+
+size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es)
+{
+    return (size_t)kBuffers * offload_slab_set_bytes(g, chunk, es);
+}
+
+template <typename T, typename C>
+int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
+                const Geom& g, T* su, T* sv, T* sw, int chunk, void* workspace, bool use_march,
+                hipStream_t stream, const char** what)
+{
+    DeviceQueues* q = nullptr;
+    hipError_t e = queues_for_current_device(&q);
+    if (e != hipSuccess) {
+        *what = "creating the offload streams";
+        return (int)e;
+    }
+    // one enqueue at a time per process: the internal streams and events are
+    // shared, and each wait captures the event's latest record when it is queued
+    std::lock_guard<std::mutex> lock(g_enqueue_mutex);
+    const size_t plane = (size_t)g.sx;                       // elements per storage plane
+    const size_t slab = (size_t)(chunk + 2 * g.h) * plane;   // elements per slab array
+    T* base = (T*)workspace;
+    auto buf = [&](int b, int f) -> T* { return base + ((size_t)b * 6 + (size_t)f) * slab; };
+    const T* in[3] = {u, v, w};
+    T* out[3] = {su, sv, sw};
+    const size_t row = (size_t)g.ny * (size_t)g.Sz * sizeof(T);   // interior columns of a plane
+    const size_t pitch = plane * sizeof(T);
+    const size_t col0 = (size_t)g.h * (size_t)g.Sz;                // first interior column in a plane
+
+    // everything starts after the work already queued on the caller's stream
+    if ((e = hipEventRecord(q->start, stream)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+    if ((e = hipStreamWaitEvent(q->h2d, q->start, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+    if ((e = hipStreamWaitEvent(q->d2h, q->start, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+
+    const int nslabs = (g.nx + chunk - 1) / chunk;
+    for (int k = 0; k < nslabs; ++k) {
+        const int b = k % kBuffers;
+        const int i0 = k * chunk;
+        const int c = g.nx - i0 < chunk ? g.nx - i0 : chunk;
+        Geom sg = g;
+        sg.nx = c;
+        sg.Sx = c + 2 * g.h;
+        // inputs: storage planes i0 .. i0 + c + 2h - 1 (interior planes i0-h .. i0+c+h-1)
+        if (k >= kBuffers && (e = hipStreamWaitEvent(q->h2d, q->done_kernel[b], 0)) != hipSuccess) {
+            *what = "hipStreamWaitEvent";
+            return (int)e;
+        }
+        for (int f = 0; f < 3; ++f) {
+            e = hipMemcpyAsync(buf(b, f), in[f] + (size_t)i0 * plane, (size_t)(c + 2 * g.h) * pitch,
+                               hipMemcpyDefault, q->h2d);
+            if (e != hipSuccess) { *what = "hipMemcpyAsync (to device)"; return (int)e; }
+        }
+        if ((e = hipEventRecord(q->done_in[b], q->h2d)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+        // kernel on the slab
+        if ((e = hipStreamWaitEvent(stream, q->done_in[b], 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+        if (k >= kBuffers && (e = hipStreamWaitEvent(stream, q->done_out[b], 0)) != hipSuccess) {
+            *what = "hipStreamWaitEvent";
+            return (int)e;
+        }
+        FwdArgs<T> a{buf(b, 0), buf(b, 1), buf(b, 2), tzc1, tzc2, tcx, tcy, buf(b, 3), buf(b, 4), buf(b, 5)};
+        (void)hipGetLastError();
+        if (use_march)
+            launch_fwd_march<T, C>(a, sg, stream);
+        else
+            launch_fwd_direct<T, C>(a, sg, stream);
+        if ((e = hipGetLastError()) != hipSuccess) { *what = "kernel launch"; return (int)e; }
+        if ((e = hipEventRecord(q->done_kernel[b], stream)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+        // outputs: interior columns of the slab's c interior planes
+        if ((e = hipStreamWaitEvent(q->d2h, q->done_kernel[b], 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+        for (int f = 0; f < 3; ++f) {
+            T* dst = out[f] + (size_t)(i0 + g.h) * plane + col0;
+            const T* src = buf(b, 3 + f) + (size_t)g.h * plane + col0;
+            e = hipMemcpy2DAsync(dst, pitch, src, pitch, row, (size_t)c, hipMemcpyDefault, q->d2h);
+            if (e != hipSuccess) { *what = "hipMemcpy2DAsync (to host)"; return (int)e; }
+        }
+        if ((e = hipEventRecord(q->done_out[b], q->d2h)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+    }
+    // later work on the caller's stream sees every copy back
+    if ((e = hipEventRecord(q->end_out, q->d2h)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+    if ((e = hipStreamWaitEvent(stream, q->end_out, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+    return 0;
+}
+
+template int offload_fwd<double, double>(const double*, const double*, const double*, const double*, const double*,
+                                         double, double, const Geom&, double*, double*, double*, int, void*, bool,
+                                         hipStream_t, const char**);
+template int offload_fwd<float, float>(const float*, const float*, const float*, const double*, const double*, double,
+                                       double, const Geom&, float*, float*, float*, int, void*, bool, hipStream_t,
+                                       const char**);
+template int offload_fwd<float, double>(const float*, const float*, const float*, const double*, const double*,
+                                        double, double, const Geom&, float*, float*, float*, int, void*, bool,
+                                        hipStream_t, const char**);

@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwadvect.so")
 
-PW_F64, PW_F32 = 0, 1
+PW_F64, PW_F32, PW_F32_F64 = 0, 1, 2
 KERNELS = {"auto": 0, "direct": 1, "march": 2}
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
           -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
@@ -37,9 +37,13 @@ lib.pw_advect_fwd_adj.argtypes = [_vp] * 8 + [_d, _d] + [_i] * 4 + [_vp] * 6 + [
 lib.pw_halo_periodic.argtypes = [_vp] + [_i] * 5 + [_vp]
 lib.pw_pad_periodic.argtypes = [_vp, _vp] + [_i] * 5 + [_vp]
 lib.pw_fill_uniform.argtypes = [_vp] + [_i] * 4 + [ctypes.c_ulonglong, _i, _d, _i, _i, _vp]
+lib.pw_advect_fwd_host.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _vp, ctypes.c_size_t,
+                                                                          _i, _vp]
+lib.pw_offload_workspace_bytes.argtypes = [_i] * 6
+lib.pw_offload_workspace_bytes.restype = ctypes.c_size_t
 lib.pw_set_kernel.argtypes = [_i]
 lib.pw_last_error.restype = ctypes.c_char_p
-for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_halo_periodic",
+for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_halo_periodic",
            "pw_pad_periodic", "pw_fill_uniform", "pw_set_kernel", "pw_get_kernel", "pw_version"):
     getattr(lib, _f).restype = ctypes.c_int
 
@@ -55,12 +59,18 @@ def _check(rc):
         raise PWError(rc, lib.pw_last_error().decode())
 
 
-def _dtype_code(t):
-    if t.dtype == torch.float64:
+def _dtype_code(t, compute=None):
+    """pw_dtype for storage dtype ``t.dtype`` (a tensor or a torch dtype) and
+    arithmetic dtype ``compute`` (None: the storage dtype)."""
+    st = t if isinstance(t, torch.dtype) else t.dtype
+    compute = st if compute is None else compute
+    if st == torch.float64 and compute == torch.float64:
         return PW_F64
-    if t.dtype == torch.float32:
+    if st == torch.float32 and compute == torch.float32:
         return PW_F32
-    raise TypeError("field tensors must be float64 or float32, got %s" % t.dtype)
+    if st == torch.float32 and compute == torch.float64:
+        return PW_F32_F64
+    raise TypeError("unsupported storage/compute dtypes %s/%s" % (st, compute))
 
 
 def _stream():
@@ -98,18 +108,19 @@ def _out(ref, t):
     return torch.zeros_like(ref) if t is None else t
 
 
-def fwd(u, v, w, tzc1, tzc2, tcx, tcy, halo, su=None, sv=None, sw=None):
-    """Forward source terms; returns (su, sv, sw) storage tensors."""
+def fwd(u, v, w, tzc1, tzc2, tcx, tcy, halo, su=None, sv=None, sw=None, compute=None):
+    """Forward source terms; returns (su, sv, sw) storage tensors.
+    ``compute=torch.float64`` with float32 fields selects PW_F32_F64."""
     nx, ny, nz = _grid(u, halo)
     su, sv, sw = _out(u, su), _out(u, sv), _out(u, sw)
     _fields(u, v, w, su, sv, sw)
     t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
     _check(lib.pw_advect_fwd(_ptr(u), _ptr(v), _ptr(w), _ptr(t1), _ptr(t2), float(tcx), float(tcy),
-                             nx, ny, nz, halo, _ptr(su), _ptr(sv), _ptr(sw), _dtype_code(u), _stream()))
+                             nx, ny, nz, halo, _ptr(su), _ptr(sv), _ptr(sw), _dtype_code(u, compute), _stream()))
     return su, sv, sw
 
 
-def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, gu=None, gv=None, gw=None):
+def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, gu=None, gv=None, gw=None, compute=None):
     """Gather-form adjoint; returns (gu, gv, gw) storage tensors."""
     nx, ny, nz = _grid(u, halo)
     gu, gv, gw = _out(u, gu), _out(u, gv), _out(u, gw)
@@ -117,11 +128,11 @@ def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, gu=None, gv=None, gw=No
     t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
     _check(lib.pw_advect_adj(_ptr(u), _ptr(v), _ptr(w), _ptr(lu), _ptr(lv), _ptr(lw), _ptr(t1), _ptr(t2),
                              float(tcx), float(tcy), nx, ny, nz, halo, _ptr(gu), _ptr(gv), _ptr(gw),
-                             _dtype_code(u), _stream()))
+                             _dtype_code(u, compute), _stream()))
     return gu, gv, gw
 
 
-def fwd_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, out=None):
+def fwd_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, out=None, compute=None):
     """Forward and adjoint in one launch; returns (su, sv, sw, gu, gv, gw)."""
     nx, ny, nz = _grid(u, halo)
     out = [None] * 6 if out is None else list(out)
@@ -130,8 +141,33 @@ def fwd_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, out=None):
     t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
     _check(lib.pw_advect_fwd_adj(_ptr(u), _ptr(v), _ptr(w), _ptr(lu), _ptr(lv), _ptr(lw), _ptr(t1),
                                  _ptr(t2), float(tcx), float(tcy), nx, ny, nz, halo,
-                                 *[_ptr(t) for t in out], _dtype_code(u), _stream()))
+                                 *[_ptr(t) for t in out], _dtype_code(u, compute), _stream()))
     return tuple(out)
+
+
+def offload_workspace_bytes(shape, halo, dtype, chunk, compute=None):
+    """Device workspace bytes that fwd_host needs for storage ``shape``."""
+    nx, ny, nz = (int(s) - 2 * halo for s in shape)
+    code = _dtype_code(dtype, compute)
+    return int(lib.pw_offload_workspace_bytes(nx, ny, nz, halo, code, int(chunk)))
+
+
+def fwd_host(u, v, w, tzc1, tzc2, tcx, tcy, halo, su, sv, sw, chunk, workspace, compute=None):
+    """Forward source terms for host storage tensors (pin them for overlap),
+    pipelined in x-slabs of ``chunk`` planes through a device ``workspace``
+    tensor; returns (su, sv, sw).  Asynchronous on the current stream."""
+    nx, ny, nz = _grid(u, halo)
+    for t in (u, v, w, su, sv, sw):
+        if t.is_cuda or not t.is_contiguous() or t.shape != u.shape or t.dtype != u.dtype:
+            raise ValueError("fwd_host takes contiguous host tensors of one storage shape and dtype")
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    t1, t2 = _profile(tzc1, nz, workspace.device), _profile(tzc2, nz, workspace.device)
+    _check(lib.pw_advect_fwd_host(_ptr(u), _ptr(v), _ptr(w), _ptr(t1), _ptr(t2), float(tcx), float(tcy),
+                                  nx, ny, nz, halo, _ptr(su), _ptr(sv), _ptr(sw), int(chunk),
+                                  _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _dtype_code(u, compute), _stream()))
+    return su, sv, sw
 
 
 def halo_periodic(storage, halo):

@@ -1,0 +1,167 @@
+"""GPU parity of the FP32-storage / FP64-arithmetic path (PW_F32_F64).
+
+The fields are stored as float; the kernels widen every operand to double
+exactly, evaluate the FP64 expression trees, and round each result to float
+once.  Consequences tested here against the oracle run in FP64 on the same
+float inputs (widened):
+  * forward: the FP64 forward equals the oracle bit for bit, so the mixed
+    forward must equal the oracle's result rounded to float, bit for bit;
+  * adjoint: within one float rounding of the oracle plus the FP64 adjoint's
+    own reordering error, |gpu - ref| <= 2^-24 |ref| + 32 * 2^-53 * T, with T
+    the sum of absolute products of the cell (the oracle's error magnitude);
+  * the fused launch, the separate launches, both kernel families and every
+    marching variant give identical bits.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _helpers import H, host_case, log, oracle_storage
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+F64 = torch.float64
+SHAPES = [(32, 32, 64, 40), (33, 17, 65, 41), (5, 7, 3, 42), (1, 9, 64, 43), (17, 1, 64, 44), (7, 130, 64, 45),
+          (2, 3, 2, 46)]
+
+
+@pytest.fixture(scope="module")
+def pw():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2010_01545_amd import pwadvect
+    return pwadvect
+
+
+def as_f32(arrs):
+    return [a.astype(np.float32) for a in arrs]
+
+
+def dev_f32(pw, arrs):
+    return [pw.pad_periodic(torch.from_numpy(np.ascontiguousarray(a)).to(DEV), H) for a in arrs]
+
+
+def coef_dev(coef):
+    return torch.from_numpy(coef[0]).to(DEV), torch.from_numpy(coef[1]).to(DEV)
+
+
+def with_kernel(pw, kernel, fn):
+    prev = pw.set_kernel(kernel)
+    try:
+        out = fn()
+    finally:
+        pw.set_kernel(prev)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def interior(a):
+    return oracle.interior(a, H)
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
+def test_fwd_is_rounded_oracle(pw, shape, kernel):
+    nx, ny, nz, seed = shape
+    if kernel == "march" and nz != 64:
+        pytest.skip("x-marching kernel is specialised for nz == 64")
+    log("mixed fwd %s %s" % (kernel, shape))
+    fields, _, coef = host_case(nx, ny, nz, seed)
+    f32 = as_f32(fields)
+    ref = oracle.fwd(*oracle_storage([a.astype(np.float64) for a in f32]), *coef, H)
+    st = dev_f32(pw, f32)
+    outs = [torch.full_like(st[0], float("nan")) for _ in range(3)]
+    got = with_kernel(pw, kernel, lambda: pw.fwd(*st, *coef_dev(coef), coef[2], coef[3], H, *outs, compute=F64))
+    for name, g, r in zip(("su", "sv", "sw"), got, ref):
+        assert g.dtype == np.float32
+        gi, ri = interior(g), interior(r).astype(np.float32)
+        assert np.array_equal(gi, ri), "%s: %d of %d cells differ" % (name, np.sum(gi != ri), gi.size)
+        col = g[H:-H, H:-H, :]
+        assert np.all(col[:, :, :H] == 0) and np.all(col[:, :, -H:] == 0), name
+        assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[:, :H])), name
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
+def test_adj_within_one_rounding(pw, shape, kernel):
+    nx, ny, nz, seed = shape
+    if kernel == "march" and nz != 64:
+        pytest.skip("x-marching kernel is specialised for nz == 64")
+    log("mixed adj %s %s" % (kernel, shape))
+    fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 9)
+    f32, l32 = as_f32(fields), as_f32(lams)
+    st_h = oracle_storage([a.astype(np.float64) for a in f32])
+    sl_h = oracle_storage([a.astype(np.float64) for a in l32])
+    ref = oracle.adj(*st_h, *sl_h, *coef, H)
+    mag = oracle.adj(*st_h, *sl_h, *coef, H, abs_bound=True)
+    st, sl = dev_f32(pw, f32), dev_f32(pw, l32)
+    got = with_kernel(pw, kernel, lambda: pw.adj(*st, *sl, *coef_dev(coef), coef[2], coef[3], H, compute=F64))
+    for name, g, r, t in zip(("gu", "gv", "gw"), got, ref, mag):
+        gi, ri, ti = interior(g).astype(np.float64), interior(r), interior(t)
+        bound = 2.0 ** -24 * np.abs(ri) + 32 * 2.0 ** -53 * ti + 1e-300
+        bad = np.abs(gi - ri) > bound
+        assert not np.any(bad), "%s: %d cells outside one FP32 rounding" % (name, np.sum(bad))
+
+
+@pytest.mark.parametrize("kernel", ["direct", "march"])
+def test_fused_equals_separate(pw, kernel):
+    fields, lams, coef = host_case(40, 24, 64, 47, lam_seed=48)
+    st, sl = dev_f32(pw, as_f32(fields)), dev_f32(pw, as_f32(lams))
+    args = coef_dev(coef) + (coef[2], coef[3], H)
+    s = with_kernel(pw, kernel, lambda: pw.fwd(*st, *args, compute=F64))
+    g = with_kernel(pw, kernel, lambda: pw.adj(*st, *sl, *args, compute=F64))
+    f = with_kernel(pw, kernel, lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
+    for a, b in zip(s + g, f):
+        assert np.array_equal(interior(a), interior(b))
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3"])
+def test_every_march_variant_matches_direct(pw, variant):
+    fields, lams, coef = host_case(45, 31, 64, 49, lam_seed=50)
+    st, sl = dev_f32(pw, as_f32(fields)), dev_f32(pw, as_f32(lams))
+    args = coef_dev(coef) + (coef[2], coef[3], H)
+    ref = with_kernel(pw, "direct", lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
+    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
+    os.environ["PW_MARCH_VARIANT"] = variant
+    os.environ["PW_MARCH_LX"] = "7"
+    try:
+        got = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
+        got_g = with_kernel(pw, "march", lambda: pw.adj(*st, *sl, *args, compute=F64))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for a, b in zip(ref, got):
+        assert np.array_equal(interior(a), interior(b))
+    for a, b in zip(ref[3:], got_g):
+        assert np.array_equal(interior(a), interior(b))
+
+
+def test_offload_mixed_matches_device_path(pw):
+    fields, _, coef = host_case(20, 13, 64, 51)
+    f32 = as_f32(fields)
+    st = dev_f32(pw, f32)
+    ref = [o.cpu().numpy() for o in pw.fwd(*st, *coef_dev(coef), coef[2], coef[3], H, compute=F64)]
+    host = []
+    for t in st:
+        h = torch.empty(t.shape, dtype=torch.float32, pin_memory=True)
+        h.copy_(t)
+        host.append(h)
+    outs = [torch.full(host[0].shape, float("nan"), dtype=torch.float32, pin_memory=True) for _ in range(3)]
+    ws = torch.empty(pw.offload_workspace_bytes(host[0].shape, H, torch.float32, 6, compute=F64),
+                     dtype=torch.uint8, device=DEV)
+    pw.fwd_host(*host, *coef_dev(coef), coef[2], coef[3], H, *outs, 6, ws, compute=F64)
+    torch.cuda.current_stream().synchronize()
+    for g, r in zip(outs, ref):
+        assert np.array_equal(g.numpy()[H:-H, H:-H], r[H:-H, H:-H])
+
+
+def test_mixed_rejects_double_storage(pw):
+    t = torch.zeros((8, 8, 68), dtype=torch.float64, device=DEV)
+    with pytest.raises(TypeError):
+        pw.fwd(t, t, t, torch.zeros(64, dtype=F64), torch.zeros(64, dtype=F64), 0.0, 0.0, H,
+               compute=torch.float32)

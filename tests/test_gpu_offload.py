@@ -1,0 +1,101 @@
+"""GPU tests of the host-resident offload path (pw_advect_fwd_host): the
+pipelined slab transfer must reproduce the device-resident forward bit for
+bit, write only interior columns of the host outputs, and order itself on the
+caller's stream."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _helpers import H, host_case, log
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pw():
+    assert torch.cuda.is_available()
+    from paper_2010_01545_amd import pwadvect
+    return pwadvect
+
+
+def _host(arr, dtype, pinned):
+    t = torch.empty(arr.shape, dtype=dtype, pin_memory=pinned)
+    t.copy_(torch.from_numpy(arr))
+    return t
+
+
+@pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,chunks", [((20, 13, 64, 31), (1, 3, 7, 20, 64)),
+                                          ((9, 6, 7, 32), (4, 9))],
+                         ids=["20x13x64", "9x6x7"])
+def test_offload_matches_device_path(pw, shape, chunks, dtype, pinned):
+    nx, ny, nz, seed = shape
+    fields, _, coef = host_case(nx, ny, nz, seed)
+    tzc1, tzc2, tcx, tcy = coef
+    st = [oracle.pad_periodic(f, H) for f in fields]       # halo-filled storage on the host
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    dev_in = [torch.from_numpy(a).to(DEV, dtype) for a in st]
+    ref = [o.cpu() for o in pw.fwd(*dev_in, t1, t2, tcx, tcy, H)]
+    host_in = [_host(a, dtype, pinned) for a in st]
+    for chunk in chunks:
+        log("offload %s %s %s chunk %d" % (shape, dtype, "pinned" if pinned else "pageable", chunk))
+        outs = [torch.full(host_in[0].shape, float("nan"), dtype=dtype, pin_memory=pinned) for _ in range(3)]
+        ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, H, dtype, chunk), dtype=torch.uint8,
+                         device=DEV)
+        pw.fwd_host(*host_in, t1, t2, tcx, tcy, H, *outs, chunk, ws)
+        torch.cuda.current_stream().synchronize()
+        for got, r in zip(outs, ref):
+            g = got.numpy()
+            rr = r.numpy()
+            assert np.array_equal(g[H:-H, H:-H], rr[H:-H, H:-H]), chunk   # interior columns incl. z halo
+            assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[-H:]))     # x halo planes untouched
+            assert np.all(np.isnan(g[:, :H])) and np.all(np.isnan(g[:, -H:]))  # y halo columns untouched
+
+
+def test_offload_orders_on_callers_stream(pw):
+    """Work queued on the stream before the call (a device fill of a tensor
+    that is then copied into the pinned input) is seen by the offload, and
+    work queued after it sees the host results."""
+    nx, ny, nz, seed = 16, 12, 64, 33
+    fields, _, coef = host_case(nx, ny, nz, seed)
+    tzc1, tzc2, tcx, tcy = coef
+    st = [oracle.pad_periodic(f, H) for f in fields]
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    ref = [o.cpu() for o in pw.fwd(*[torch.from_numpy(a).to(DEV) for a in st], t1, t2, tcx, tcy, H)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dev = [torch.from_numpy(a).to(DEV, non_blocking=False) for a in st]
+        host_in = [torch.empty(a.shape, dtype=torch.float64, pin_memory=True) for a in st]
+        for hsrc, d in zip(host_in, dev):
+            hsrc.copy_(d, non_blocking=True)                 # queued on s before the offload
+        outs = [torch.zeros(host_in[0].shape, dtype=torch.float64, pin_memory=True) for _ in range(3)]
+        ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, H, torch.float64, 5), dtype=torch.uint8,
+                         device=DEV)
+        pw.fwd_host(*host_in, t1, t2, tcx, tcy, H, *outs, 5, ws)
+        back = [torch.empty_like(o, device=DEV) for o in outs]
+        for b, o in zip(back, outs):
+            b.copy_(o, non_blocking=True)                    # queued on s after the offload
+    s.synchronize()
+    for b, r in zip(back, ref):
+        assert np.array_equal(b.cpu().numpy()[H:-H, H:-H], r.numpy()[H:-H, H:-H])
+
+
+def test_offload_argument_errors(pw):
+    shape = (8 + 2 * H, 6 + 2 * H, 64 + 2 * H)
+    host = [torch.zeros(shape, dtype=torch.float64) for _ in range(6)]
+    t = torch.zeros(64, dtype=torch.float64, device=DEV)
+    need = pw.offload_workspace_bytes(shape, H, torch.float64, 3)
+    small = torch.empty(need - 8, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pw.PWError) as e:
+        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, *host[3:], 3, small)
+    assert e.value.code == -4
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pw.PWError) as e:
+        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, host[0], host[4], host[5], 3, ws)
+    assert e.value.code == -2
+    with pytest.raises(pw.PWError) as e:
+        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, *host[3:], 0, ws)
+    assert e.value.code == -1
