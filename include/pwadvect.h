@@ -147,8 +147,8 @@ int pw_advect_fwd_adj(const void *u, const void *v, const void *w,
  * `stream`; the copies use two streams the library creates once per device and
  * keeps until the process ends (default priority).  Concurrent calls are
  * serialized while they are queued.  Results are identical to pw_advect_fwd on
- * the same data.  Errors as for pw_advect_fwd; PW_ERR_SIZE if the workspace is
- * too small.
+ * the same data.  Errors as for pw_advect_fwd; PW_ERR_ARG if a field array is
+ * device memory, PW_ERR_SIZE if the workspace is too small.
  */
 size_t pw_offload_workspace_bytes(int nx, int ny, int nz, int halo, int dtype, int chunk);
 int pw_advect_fwd_host(const void *u, const void *v, const void *w,

@@ -95,6 +95,23 @@ int check_host_side(const Arr* in, int nin, const Arr* out, int nout)
 }
 
 // Device-pointer and allocation-extent checks (host queries, no GPU work).
+// Host arrays of pw_advect_fwd_host: pageable or pinned host memory, never
+// device memory (the copies are issued as host<->device transfers).
+int check_host_memory(const Arr* arrs, int n)
+{
+    for (int q = 0; q < n; q++) {
+        hipPointerAttribute_t attr;
+        std::memset(&attr, 0, sizeof attr);
+        if (hipPointerGetAttributes(&attr, arrs[q].p) != hipSuccess) {
+            (void)hipGetLastError();   // unknown to the runtime: pageable host memory
+            continue;
+        }
+        if (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeArray)
+            return fail(PW_ERR_ARG, "%s is device memory; pw_advect_fwd_host takes host arrays", arrs[q].name);
+    }
+    return PW_OK;
+}
+
 int check_device(const Arr* arrs, int n)
 {
     for (int q = 0; q < n; q++) {
@@ -306,6 +323,9 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
     const Arr in[3] = {{u, bytes, es, "u"}, {v, bytes, es, "v"}, {w, bytes, es, "w"}};
     const Arr out[3] = {{su, bytes, es, "su"}, {sv, bytes, es, "sv"}, {sw, bytes, es, "sw"}};
     rc = check_host_side(in, 3, out, 3);
+    if (rc) return rc;
+    const Arr host[6] = {in[0], in[1], in[2], out[0], out[1], out[2]};
+    rc = check_host_memory(host, 6);
     if (rc) return rc;
     const Arr dev[3] = {{tzc1, (size_t)nz * 8, 8, "tzc1"}, {tzc2, (size_t)nz * 8, 8, "tzc2"},
                         {workspace, need, 16, "workspace"}};

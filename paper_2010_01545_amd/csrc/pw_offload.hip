@@ -121,7 +121,7 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
         }
         for (int f = 0; f < 3; ++f) {
             e = hipMemcpyAsync(buf(b, f), in[f] + (size_t)i0 * plane, (size_t)(c + 2 * g.h) * pitch,
-                               hipMemcpyDefault, q->h2d);
+                               hipMemcpyHostToDevice, q->h2d);
             if (e != hipSuccess) { *what = "hipMemcpyAsync (to device)"; return (int)e; }
         }
         if ((e = hipEventRecord(q->done_in[b], q->h2d)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
@@ -144,7 +144,7 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
         for (int f = 0; f < 3; ++f) {
             T* dst = out[f] + (size_t)(i0 + g.h) * plane + col0;
             const T* src = buf(b, 3 + f) + (size_t)g.h * plane + col0;
-            e = hipMemcpy2DAsync(dst, pitch, src, pitch, row, (size_t)c, hipMemcpyDefault, q->d2h);
+            e = hipMemcpy2DAsync(dst, pitch, src, pitch, row, (size_t)c, hipMemcpyDeviceToHost, q->d2h);
             if (e != hipSuccess) { *what = "hipMemcpy2DAsync (to host)"; return (int)e; }
         }
         if ((e = hipEventRecord(q->done_out[b], q->d2h)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }

@@ -99,3 +99,10 @@ def test_offload_argument_errors(pw):
     with pytest.raises(pw.PWError) as e:
         pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, *host[3:], 0, ws)
     assert e.value.code == -1
+    # a device array in place of a host one is refused (the binding would
+    # refuse it too, so call the C entry point directly)
+    d = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    p = [pw._ptr(x) for x in host]
+    rc = pw.lib.pw_advect_fwd_host(p[0], p[1], pw._ptr(d), pw._ptr(t), pw._ptr(t), -0.005, -0.005,
+                                   8, 6, 64, H, p[3], p[4], p[5], 3, pw._ptr(ws), need, 0, pw._stream())
+    assert rc == -1 and b"device memory" in pw.lib.pw_last_error()
