@@ -35,7 +35,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {  # algorithmic: each input read once, each output written once
     ("fwd", 8): 48, ("adj", 8): 72, ("fused", 8): 96,
     ("fwd", 4): 24, ("adj", 4): 36, ("fused", 4): 48,
+    # Euler step u + dt*su fused into the forward: reads u, v, w, writes the
+    # new fields (the same streams as the forward); unfused it is the forward
+    # plus a pass reading u and su and writing the new field (+72 B FP64)
+    ("update", 8): 48, ("update", 4): 24, ("fwd+axpy", 8): 120, ("fwd+axpy", 4): 60,
 }
+DT = 0.5   # timestep of the update path (any value: the timing does not depend on it)
 
 
 def log(msg):
@@ -92,7 +97,14 @@ class Grid:
 
     def launch(self, pw, path):
         c = self.compute
-        if path == "fwd":
+        if path == "update":
+            pw.fwd_update(*self.f, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.f, DT, *self.s, compute=c)
+        elif path == "fwd+axpy":
+            import torch
+            pw.fwd(*self.f, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.s, compute=c)
+            for f, sq in zip(self.f, self.s):
+                torch.add(f, sq, alpha=DT, out=sq)
+        elif path == "fwd":
             pw.fwd(*self.f, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.s, compute=c)
         elif path == "adj":
             pw.adj(*self.f, *self.l, self.t1, self.t2, self.tcx, self.tcy, self.h, *self.g, compute=c)
@@ -203,7 +215,16 @@ def offload_measure(pw, torch, reps=3, chunk=64):
         return ev[0].elapsed_time(ev[1]) / n
 
     run = lambda: pw.fwd_host(*host_in, g.t1, g.t2, g.tcx, g.tcy, h, *host_out, chunk, ws)
-    t_off = timed(run, reps)
+    t_off = timed(run, reps)                     # library's copy kernel writes the pinned outputs
+    old = os.environ.get("PW_OFFLOAD_COPY_OUT")
+    os.environ["PW_OFFLOAD_COPY_OUT"] = "runtime"   # the runtime's copies instead
+    try:
+        t_off_rt = timed(run, reps)
+    finally:
+        if old is None:
+            os.environ.pop("PW_OFFLOAD_COPY_OUT")
+        else:
+            os.environ["PW_OFFLOAD_COPY_OUT"] = old
     t_h2d = timed(lambda: [d.copy_(hsrc, non_blocking=True) for d, hsrc in zip(g.f, host_in)], reps)
     t_d2h = timed(lambda: [o.copy_(d, non_blocking=True) for o, d in zip(host_out, g.s)], reps)
     t_k = timed(lambda: g.launch(pw, "fwd"), reps)
@@ -214,9 +235,11 @@ def offload_measure(pw, torch, reps=3, chunk=64):
         "cells": cells,
         "gcells_per_s_incl_transfers": cells / (t_off * 1e-3) / 1e9,
         "ms_pipelined": t_off,
+        "ms_pipelined_runtime_copy_out": t_off_rt,
         "ms_copy_in_alone": t_h2d, "ms_copy_out_alone": t_d2h, "ms_kernel_alone": t_k,
         "copy_in_GBps": nbytes / (t_h2d * 1e-3) / 1e9, "copy_out_GBps": nbytes / (t_d2h * 1e-3) / 1e9,
         "overlap": (t_h2d + t_d2h + t_k) / t_off,
+        "ideal_ms": max(t_h2d, t_d2h),
         "bytes_each_way": nbytes,
     }
     del g, host_in, host_out, ws
@@ -293,7 +316,7 @@ def main():
 
     paths = {"fused_f64": head}
     if not args.no_paths:
-        for p in ("fwd", "adj"):
+        for p in ("fwd", "adj", "update", "fwd+axpy"):
             g.launch(pw, p)
             paths[p + "_f64"] = path_record(p, 8, cells, time_launches(torch, lambda: g.launch(pw, p),
                                                                        args.paths_reps))
@@ -347,8 +370,9 @@ def main():
     if not args.no_offload:
         log("bench: host-resident offload at 4096x1024x64")
         out["offload"] = offload_measure(pw, torch)
-        log("bench: offload %.1f ms pipelined (in %.1f, kernel %.1f, out %.1f)" % (
-            out["offload"]["ms_pipelined"], out["offload"]["ms_copy_in_alone"],
+        log("bench: offload %.1f ms pipelined, %.1f with runtime copies out (in %.1f, kernel %.1f, out %.1f)" % (
+            out["offload"]["ms_pipelined"], out["offload"]["ms_pipelined_runtime_copy_out"],
+            out["offload"]["ms_copy_in_alone"],
             out["offload"]["ms_kernel_alone"], out["offload"]["ms_copy_out_alone"]))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle")

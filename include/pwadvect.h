@@ -129,6 +129,31 @@ int pw_advect_fwd_adj(const void *u, const void *v, const void *w,
                       int dtype, void *stream);
 
 /*
+ * Forward source terms combined with their use later in the timestep (section
+ * 2.1: after the dynamical core the source terms are integrated into the flow
+ * fields).  Writes, on interior cells,
+ *     ou = bu + beta*su,   ov = bv + beta*sv,   ow = bw + beta*sw
+ * with su, sv, sw the values pw_advect_fwd gives (they are not stored), the
+ * product and the sum each rounded once in the arithmetic type (no fused
+ * multiply-add), then rounded to the element type.  z-halo levels of interior
+ * columns of o get 0; x/y halo columns of o are not written.  Uses:
+ *   accumulate   b = o (the same pointers), beta = 1: adds the advective
+ *                tendency to source terms that other schemes already hold;
+ *                each element is read before the same thread writes it.
+ *   Euler step   b = (u, v, w) (the same pointers), o = new arrays, beta = dt:
+ *                u + dt*su in one pass; the kernels reuse the field values they
+ *                read, so the call moves the bytes of pw_advect_fwd.
+ * Any other b must not overlap an output; o must not overlap u, v, w (their
+ * neighbours are still being read).  Errors as for pw_advect_fwd; PW_ERR_ALIAS
+ * also for a b array that overlaps an output other than its own.
+ */
+int pw_advect_fwd_update(const void *u, const void *v, const void *w,
+                         const double *tzc1, const double *tzc2, double tcx, double tcy,
+                         int nx, int ny, int nz, int halo,
+                         const void *bu, const void *bv, const void *bw, double beta,
+                         void *ou, void *ov, void *ow, int dtype, void *stream);
+
+/*
  * Forward source terms for fields held in HOST memory: the offload measured in
  * the paper's sections 4 and 5 (winds copied to the accelerator, kernel, source
  * terms copied back), with the transfer cut into x-slabs of `chunk` planes and
@@ -145,7 +170,11 @@ int pw_advect_fwd_adj(const void *u, const void *v, const void *w,
  * The call is asynchronous on `stream`: it starts after the work already queued
  * there, and work queued there afterwards sees every result.  Kernels run on
  * `stream`; the copies use two streams the library creates once per device and
- * keeps until the process ends (default priority).  Concurrent calls are
+ * keeps until the process ends (default priority).  Inputs go in through the
+ * runtime's host-to-device copies.  Outputs that are pinned host memory mapped
+ * into the device's address space are written back by a copy kernel of the
+ * library (PW_OFFLOAD_COPY_OUT=runtime in the environment selects the
+ * runtime's copies instead); other outputs by the runtime's copies.  Concurrent calls are
  * serialized while they are queued.  Results are identical to pw_advect_fwd on
  * the same data.  Errors as for pw_advect_fwd; PW_ERR_ARG if a field array is
  * device memory, PW_ERR_SIZE if the workspace is too small.

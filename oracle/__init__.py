@@ -96,6 +96,23 @@ def fwd(u, v, w, tzc1, tzc2, tcx, tcy, h, threaded=False, abs_bound=False):
     return tuple(outs)
 
 
+def fwd_update(u, v, w, tzc1, tzc2, tcx, tcy, h, bu, bv, bw, beta):
+    """Use of the source terms in the timestep (section 2.1: they are
+    integrated into the flow fields after the dynamical core): storage arrays
+    whose interior cells hold b + beta * s, the product and the sum each
+    rounded in FP64 (numpy evaluates them as two operations), and whose halo
+    cells are zero.  b arrays are storage arrays (only interiors are used)."""
+    s = fwd(u, v, w, tzc1, tzc2, tcx, tcy, h)
+    outs = []
+    for b, sq in zip((bu, bv, bw), s):
+        o = np.zeros_like(sq)
+        ob = np.asarray(b, dtype=np.float64)
+        t = np.multiply(np.float64(beta), sq[h:-h, h:-h, h:-h])
+        o[h:-h, h:-h, h:-h] = np.add(ob[h:-h, h:-h, h:-h], t)
+        outs.append(o)
+    return tuple(outs)
+
+
 def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, h, abs_bound=False):
     """Gradient of sum(lu*su + lv*sv + lw*sw) over interior cells with respect
     to the interior fields of the x/y-periodic problem, as storage arrays whose

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/pwadvect.h"
@@ -95,6 +96,29 @@ int check_host_side(const Arr* in, int nin, const Arr* out, int nout)
 }
 
 // Device-pointer and allocation-extent checks (host queries, no GPU work).
+// Device address of a pinned host array that is mapped into the current
+// device's address space and lies wholly inside one allocation; nullptr
+// otherwise (pageable memory, unknown extent).
+void* mapped_host(const void* p, size_t bytes)
+{
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (attr.type != hipMemoryTypeHost || !attr.devicePointer) return nullptr;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)attr.devicePointer) != hipSuccess || size == 0) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const uintptr_t b = (uintptr_t)base, d = (uintptr_t)attr.devicePointer;
+    if (d < b || d + bytes > b + size) return nullptr;
+    return attr.devicePointer;
+}
+
 // Host arrays of pw_advect_fwd_host: pageable or pinned host memory, never
 // device memory (the copies are issued as host<->device transfers).
 int check_host_memory(const Arr* arrs, int n)
@@ -158,29 +182,61 @@ int resolve_kernel(const Geom& g, const Arr* arrs, int n)
     return march ? PW_KERNEL_MARCH : PW_KERNEL_DIRECT;
 }
 
+// base == nullptr: plain forward.  Otherwise the update form o = b + beta * s
+// (pw_advect_fwd_update): b[q] is o[q] itself, or an array that overlaps no
+// output; b == (u, v, w) selects the kernels' field-reuse mode.
 template <typename T, typename C>
 int do_fwd(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
            double tcx, double tcy, const Geom& g, size_t bytes, void* su, void* sv, void* sw,
-           hipStream_t stream)
+           hipStream_t stream, const void* const* base = nullptr, double beta = 0.0)
 {
     const Arr in[5] = {{u, bytes, sizeof(T), "u"}, {v, bytes, sizeof(T), "v"}, {w, bytes, sizeof(T), "w"},
                        {tzc1, (size_t)g.nz * 8, 8, "tzc1"}, {tzc2, (size_t)g.nz * 8, 8, "tzc2"}};
     const Arr out[3] = {{su, bytes, sizeof(T), "su"}, {sv, bytes, sizeof(T), "sv"}, {sw, bytes, sizeof(T), "sw"}};
     int rc = check_host_side(in, 5, out, 3);
     if (rc) return rc;
+    static const char* const names[3] = {"bu", "bv", "bw"};
+    Arr ba[3];
+    if (base) {   // host-side checks of the base arrays before any device query
+        for (int q = 0; q < 3; q++) ba[q] = Arr{base[q], bytes, sizeof(T), names[q]};
+        rc = check_host_side(ba, 3, nullptr, 0);
+        if (rc) return rc;
+        for (int q = 0; q < 3; q++) {
+            if (base[q] == out[q].p) continue;   // accumulate in place
+            const uintptr_t bb = (uintptr_t)base[q], be = bb + bytes;
+            for (int o = 0; o < 3; o++) {
+                const uintptr_t ob = (uintptr_t)out[o].p, oe = ob + bytes;
+                if (bb < oe && ob < be)
+                    return fail(PW_ERR_ALIAS, "%s overlaps output %s (only %s itself may be passed as %s)",
+                                names[q], out[o].name, out[q].name, names[q]);
+            }
+        }
+    }
     const Arr all[8] = {in[0], in[1], in[2], in[3], in[4], out[0], out[1], out[2]};
     rc = check_device(all, 8);
     if (rc) return rc;
-    const Arr fields[6] = {in[0], in[1], in[2], out[0], out[1], out[2]};
-    const int kern = resolve_kernel<T>(g, fields, 6);
+    Arr fields[9] = {in[0], in[1], in[2], out[0], out[1], out[2]};
+    int nf = 6;
+    int upd = 0;
+    if (base) {
+        rc = check_device(ba, 3);
+        if (rc) return rc;
+        upd = (base[0] == u && base[1] == v && base[2] == w) ? 2 : 1;
+        if (upd == 1)
+            for (int q = 0; q < 3; q++) fields[nf++] = ba[q];
+    }
+    const int kern = resolve_kernel<T>(g, fields, nf);
     if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64 and 16-byte aligned arrays");
-    FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw};
+    FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw, upd,
+                 {nullptr, nullptr, nullptr}, beta};
+    if (base)
+        for (int q = 0; q < 3; q++) a.b[q] = (const T*)base[q];
     (void)hipGetLastError();
     if (kern == PW_KERNEL_MARCH)
         launch_fwd_march<T, C>(a, g, stream);
     else
         launch_fwd_direct<T, C>(a, g, stream);
-    return launched("pw_advect_fwd");
+    return launched(base ? "pw_advect_fwd_update" : "pw_advect_fwd");
 }
 
 template <typename T, typename C>
@@ -252,6 +308,26 @@ int pw_advect_fwd(const void* u, const void* v, const void* w, const double* tzc
     if (dtype == PW_F32_F64)
         return do_fwd<float, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
     return do_fwd<float, float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+}
+
+int pw_advect_fwd_update(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
+                         double tcx, double tcy, int nx, int ny, int nz, int halo, const void* bu,
+                         const void* bv, const void* bw, double beta, void* ou, void* ov, void* ow, int dtype,
+                         void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    const void* const base[3] = {bu, bv, bw};
+    if (dtype == PW_F64)
+        return do_fwd<double, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow, (hipStream_t)stream,
+                                      base, beta);
+    if (dtype == PW_F32_F64)
+        return do_fwd<float, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow, (hipStream_t)stream,
+                                     base, beta);
+    return do_fwd<float, float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow, (hipStream_t)stream, base,
+                                beta);
 }
 
 int pw_advect_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
@@ -339,21 +415,33 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
     const Arr ws[1] = {{workspace, need, 16, "workspace"}};
     const int kern = storage_is_double(dtype) ? resolve_kernel<double>(sg, ws, 1) : resolve_kernel<float>(sg, ws, 1);
     if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64");
+    // mapped pinned outputs are written by a copy kernel unless
+    // PW_OFFLOAD_COPY_OUT=runtime asks for the runtime's copies
+    void* od[3] = {nullptr, nullptr, nullptr};
+    const char* env = std::getenv("PW_OFFLOAD_COPY_OUT");
+    bool mapped = !(env && std::strcmp(env, "runtime") == 0);
+    for (int f = 0; f < 3 && mapped; ++f) mapped = (od[f] = mapped_host(out[f].p, bytes)) != nullptr;
     const char* what = "";
     int e;
     const bool march = kern == PW_KERNEL_MARCH;
-    if (dtype == PW_F64)
+    if (dtype == PW_F64) {
+        double* const o[3] = {(double*)od[0], (double*)od[1], (double*)od[2]};
         e = offload_fwd<double, double>((const double*)u, (const double*)v, (const double*)w, tzc1, tzc2, tcx,
-                                        tcy, g, (double*)su, (double*)sv, (double*)sw, chunk, workspace, march,
-                                        (hipStream_t)stream, &what);
-    else if (dtype == PW_F32_F64)
-        e = offload_fwd<float, double>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx, tcy,
-                                       g, (float*)su, (float*)sv, (float*)sw, chunk, workspace, march,
-                                       (hipStream_t)stream, &what);
-    else
-        e = offload_fwd<float, float>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx, tcy, g,
-                                      (float*)su, (float*)sv, (float*)sw, chunk, workspace, march,
-                                      (hipStream_t)stream, &what);
+                                        tcy, g, (double*)su, (double*)sv, (double*)sw, mapped ? o : nullptr, chunk,
+                                        workspace, march, (hipStream_t)stream, &what);
+    } else {
+        float* const o[3] = {(float*)od[0], (float*)od[1], (float*)od[2]};
+        if (dtype == PW_F32_F64)
+            e = offload_fwd<float, double>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx,
+                                           tcy, g, (float*)su, (float*)sv, (float*)sw,
+                                           mapped ? o : nullptr, chunk, workspace, march, (hipStream_t)stream,
+                                           &what);
+        else
+            e = offload_fwd<float, float>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx, tcy,
+                                          g, (float*)su, (float*)sv, (float*)sw,
+                                          mapped ? o : nullptr, chunk, workspace, march, (hipStream_t)stream,
+                                          &what);
+    }
     if (e) return fail(PW_ERR_HIP, "pw_advect_fwd_host: %s: %s", what, hipGetErrorString((hipError_t)e));
     return launched("pw_advect_fwd_host");
 }

@@ -56,7 +56,10 @@ __device__ __forceinline__ Star<C> widen(const Star<T>& s)
     return Star<C>{(C)s.c, (C)s.xm, (C)s.xp, (C)s.ym, (C)s.yp, (C)s.zm, (C)s.zp, (C)s.d1, (C)s.d2};
 }
 
-template <typename T, typename C>
+// UPD: 0 stores s; 1 stores b + beta * s with b loaded from a.b (which may be
+// the output array itself: the element is read before it is written); 2 the
+// same with b = (u, v, w), reusing the star centres.
+template <typename T, typename C, int UPD>
 __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -78,6 +81,15 @@ __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g
         const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, k, g.nz);
         C su, sv, sw;
         pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
+        if (UPD != 0) {
+            const C beta = (C)a.beta;
+            const C bu = UPD == 2 ? u.c : (C)a.b[0][b];
+            const C bv = UPD == 2 ? v.c : (C)a.b[1][b];
+            const C bw = UPD == 2 ? w.c : (C)a.b[2][b];
+            su = pw_update(bu, beta, su);
+            sv = pw_update(bv, beta, sv);
+            sw = pw_update(bw, beta, sw);
+        }
         a.su[b] = (T)su;
         a.sv[b] = (T)sv;
         a.sw[b] = (T)sw;
@@ -140,7 +152,12 @@ inline dim3 direct_grid(const Geom& g)
 template <typename T, typename C>
 void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
 {
-    hipLaunchKernelGGL((fwd_direct_kernel<T, C>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+    if (a.upd == 1)
+        hipLaunchKernelGGL((fwd_direct_kernel<T, C, 1>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+    else if (a.upd == 2)
+        hipLaunchKernelGGL((fwd_direct_kernel<T, C, 2>), direct_grid(g), dim3(kBlock), 0, s, a, g);
+    else
+        hipLaunchKernelGGL((fwd_direct_kernel<T, C, 0>), direct_grid(g), dim3(kBlock), 0, s, a, g);
 }
 
 template <typename T, typename C>

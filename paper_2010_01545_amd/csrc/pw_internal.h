@@ -14,12 +14,18 @@ struct Geom {
 // Operand bundles passed to the kernel launchers.  T is the storage type;
 // the kernels are also templated on the arithmetic type C (C = T, or
 // T = float with C = double), and round tcx, tcy and the profiles to C.
+// With `upd` != 0 the forward stores o = b + beta * s instead of s (b[q] is a
+// base array, possibly the output itself; upd == 2 means b is (u, v, w) and
+// the kernels reuse the values they read).
 template <typename T>
 struct FwdArgs {
     const T *u, *v, *w;
     const double *tzc1, *tzc2;
     double tcx, tcy;
     T *su, *sv, *sw;
+    int upd;
+    const T* b[3];
+    double beta;
 };
 
 template <typename T>
@@ -48,9 +54,11 @@ template <typename T> void launch_fill_uniform(T* st, const Geom& g, unsigned lo
                                                int field_id, double amp, int zero_lids,
                                                hipStream_t s);
 
-// Host-resident fields: chunked, pipelined forward (pw_offload.hip).
+// Host-resident fields: chunked, pipelined forward (pw_offload.hip).  out_dev
+// holds the device addresses of su, sv, sw when they are mapped pinned host
+// memory (a copy kernel then writes them), else nullptr (runtime copies).
 size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es);
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
-                const Geom& g, T* su, T* sv, T* sw, int chunk, void* workspace, bool use_march,
+                const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
                 hipStream_t stream, const char** what);

@@ -115,22 +115,29 @@ struct MarchArgs {
     const T* in[NF];   // u, v, w [, lu, lv, lw]
     T* s[3];           // su, sv, sw (or unused)
     T* gr[3];          // gu, gv, gw (or unused)
+    const T* b[3];     // base arrays of the update form (or unused)
     const double* tzc1;
     const double* tzc2;
-    double tcx, tcy;
+    double tcx, tcy, beta;
 };
 
 // T: storage type (registers, LDS and DPP shifts work in it); C: arithmetic
 // type (T, or double for float storage).  TY: compute columns per workgroup
 // (TY + 2 wavefronts); D: planes prefetched beyond the current xp plane (D >= 2).
-template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D>
+// UPD (forward only): 0 stores s; 1 stores b + beta * s with the base arrays
+// b streamed through the register ring like the fields (b may be the output
+// itself: each element is read planes before the same wave writes it); 2 the
+// same with b = (u, v, w), whose centre values are already in the ring.
+template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD = 0>
 __global__ void __launch_bounds__(64 * (TY + 2))
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 {
     static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
+    static_assert(UPD == 0 || (NF == 3 && WS && !WG), "the update form is a forward-only epilogue");
     constexpr int NCOL = TY + 2;
     constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
     constexpr int U = D + 3;        // register ring length
+    constexpr int NR = NF + (UPD == 1 ? 3 : 0);   // ring rows: fields, then base arrays
     __shared__ T s_uw[2 * NT][2][NCOL][NZ];
     __shared__ T s_v[NT][3][NCOL][NZ];
 
@@ -176,16 +183,17 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     // that the prefetch is not waited for at the load.
     const bool live_uv = lam_uv_live(lane, NZ), live_w = lam_w_live(lane, NZ);
     auto mask = [&](int f, T x) -> T {
-        if (f < 3) return x;
+        if (f < 3 || f >= NF) return x;
         return ((f == 5) ? live_w : live_uv) ? x : T(0);
     };
     auto ld = [&](int f, int p, int dj, int bytes) -> T {
-        return buf_load<T>(column_rsrc(column(a.in[f], p, dj), bytes), voff);
+        const T* src = f < NF ? a.in[f] : a.b[f - NF];
+        return buf_load<T>(column_rsrc(column(src, p, dj), bytes), voff);
     };
 
-    T R[NF][U];
+    T R[NR][U];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NR; ++f)
 #pragma unroll
         for (int t = 0; t < D + 2; ++t) R[f][t] = mask(f, ld(f, i0 - 1 + t, 0, ldbytes));
     T carry[NF];
@@ -224,7 +232,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 
             // prefetch plane p + D + 1
 #pragma unroll
-            for (int f = 0; f < NF; ++f) R[f][rnew] = ld(f, p + D + 1, 0, ldbytes);
+            for (int f = 0; f < NR; ++f) R[f][rnew] = ld(f, p + D + 1, 0, ldbytes);
 
             // first use of planes p+1 (all fields) and p+2 (v-type deposit)
 #pragma unroll
@@ -285,7 +293,9 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 if ((q < 3 && !WS) || (q >= 3 && !WG)) continue;
                 T* const dst = q < 3 ? a.s[q] : a.gr[q - 3];
                 const rsrc_t r = column_rsrc(column(dst, p, 0), stbytes);
-                buf_store((T)out[q], r, voff);
+                C o = out[q];
+                if (UPD != 0 && q < 3) o = pw_update((C)R[UPD == 2 ? q : NF + q][rc], (C)a.beta, o);
+                buf_store((T)o, r, voff);
                 buf_store(T(0), r, vpad);
             }
 
@@ -337,15 +347,15 @@ constexpr int lds_bytes()
     return (int)sizeof(T) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
 }
 
-template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D>
+template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD>
 void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
     if constexpr (lds_bytes<T, NF, TY>() <= 65536) {
         const Launch l = plan(g, TY);
-        hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D>), dim3(l.grid), dim3(64 * (TY + 2)), 0, s, m,
-                           g, l.LX, l.nstrips, l.nblocks);
+        hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, UPD>), dim3(l.grid), dim3(64 * (TY + 2)), 0,
+                           s, m, g, l.LX, l.nstrips, l.nblocks);
     } else {
-        go<T, C, NF, WS, WG, kTY[0], kD[0]>(m, g, s);
+        go<T, C, NF, WS, WG, kTY[0], kD[0], UPD>(m, g, s);
     }
 }
 
@@ -360,7 +370,7 @@ int default_variant()
     return (NF == 3 || (sizeof(T) == 4 && sizeof(C) == 4)) ? 2 : 0;
 }
 
-template <typename T, typename C, int NF, bool WS, bool WG>
+template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
     int v = default_variant<T, C, NF>();
@@ -369,10 +379,10 @@ void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
         if (q >= 0 && q < kVariants) v = q;
     }
     switch (v) {
-    case 1: go<T, C, NF, WS, WG, kTY[1], kD[1]>(m, g, s); break;
-    case 2: go<T, C, NF, WS, WG, kTY[2], kD[2]>(m, g, s); break;
-    case 3: go<T, C, NF, WS, WG, kTY[3], kD[3]>(m, g, s); break;
-    default: go<T, C, NF, WS, WG, kTY[0], kD[0]>(m, g, s); break;
+    case 1: go<T, C, NF, WS, WG, kTY[1], kD[1], UPD>(m, g, s); break;
+    case 2: go<T, C, NF, WS, WG, kTY[2], kD[2], UPD>(m, g, s); break;
+    case 3: go<T, C, NF, WS, WG, kTY[3], kD[3], UPD>(m, g, s); break;
+    default: go<T, C, NF, WS, WG, kTY[0], kD[0], UPD>(m, g, s); break;
     }
 }
 
@@ -395,11 +405,18 @@ void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
     m.s[1] = a.sv;
     m.s[2] = a.sw;
     m.gr[0] = m.gr[1] = m.gr[2] = nullptr;
+    for (int q = 0; q < 3; ++q) m.b[q] = a.b[q];
     m.tzc1 = a.tzc1;
     m.tzc2 = a.tzc2;
     m.tcx = a.tcx;
     m.tcy = a.tcy;
-    dispatch<T, C, 3, true, false>(m, g, s);
+    m.beta = a.beta;
+    if (a.upd == 1)
+        dispatch<T, C, 3, true, false, 1>(m, g, s);
+    else if (a.upd == 2)
+        dispatch<T, C, 3, true, false, 2>(m, g, s);
+    else
+        dispatch<T, C, 3, true, false, 0>(m, g, s);
 }
 
 template <typename T, typename C>
@@ -418,10 +435,12 @@ void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
     m.gr[0] = a.gu;
     m.gr[1] = a.gv;
     m.gr[2] = a.gw;
+    m.b[0] = m.b[1] = m.b[2] = nullptr;
     m.tzc1 = a.tzc1;
     m.tzc2 = a.tzc2;
     m.tcx = a.tcx;
     m.tcy = a.tcy;
+    m.beta = 0.0;
     if (a.su)
         dispatch<T, C, 6, true, true>(m, g, s);
     else

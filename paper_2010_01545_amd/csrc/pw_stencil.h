@@ -188,3 +188,15 @@ __device__ __forceinline__ void pw_adj_cell(const Star<T>& u, const Star<T>& v, 
     g = fmad(cf.t1k, lw.c * w.zm, g);
     gw = fmad(-cf.t2km, lw.zm * fmad(two, w.c, w.zm), g);
 }
+
+// Use of a source term in the timestep (the integration that follows the
+// dynamical core, section 2.1): base + beta * s, with the product and the sum
+// each rounded (no fused multiply-add), so that the result is the plain
+// two-operation expression.
+template <typename T>
+__device__ __forceinline__ T pw_update(T base, T beta, T s)
+{
+#pragma clang fp contract(off)
+    const T t = beta * s;
+    return base + t;
+}

@@ -34,6 +34,7 @@ _d = ctypes.c_double
 lib.pw_advect_fwd.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _vp]
 lib.pw_advect_adj.argtypes = [_vp] * 8 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _vp]
 lib.pw_advect_fwd_adj.argtypes = [_vp] * 8 + [_d, _d] + [_i] * 4 + [_vp] * 6 + [_i, _vp]
+lib.pw_advect_fwd_update.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_d] + [_vp] * 3 + [_i, _vp]
 lib.pw_halo_periodic.argtypes = [_vp] + [_i] * 5 + [_vp]
 lib.pw_pad_periodic.argtypes = [_vp, _vp] + [_i] * 5 + [_vp]
 lib.pw_fill_uniform.argtypes = [_vp] + [_i] * 4 + [ctypes.c_ulonglong, _i, _d, _i, _i, _vp]
@@ -43,7 +44,7 @@ lib.pw_offload_workspace_bytes.argtypes = [_i] * 6
 lib.pw_offload_workspace_bytes.restype = ctypes.c_size_t
 lib.pw_set_kernel.argtypes = [_i]
 lib.pw_last_error.restype = ctypes.c_char_p
-for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_halo_periodic",
+for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_advect_fwd_update", "pw_halo_periodic",
            "pw_pad_periodic", "pw_fill_uniform", "pw_set_kernel", "pw_get_kernel", "pw_version"):
     getattr(lib, _f).restype = ctypes.c_int
 
@@ -118,6 +119,21 @@ def fwd(u, v, w, tzc1, tzc2, tcx, tcy, halo, su=None, sv=None, sw=None, compute=
     _check(lib.pw_advect_fwd(_ptr(u), _ptr(v), _ptr(w), _ptr(t1), _ptr(t2), float(tcx), float(tcy),
                              nx, ny, nz, halo, _ptr(su), _ptr(sv), _ptr(sw), _dtype_code(u, compute), _stream()))
     return su, sv, sw
+
+
+def fwd_update(u, v, w, tzc1, tzc2, tcx, tcy, halo, bu, bv, bw, beta, ou=None, ov=None, ow=None,
+               compute=None):
+    """o = b + beta * s for the forward source terms s (not stored); returns
+    (ou, ov, ow).  Pass o as b to accumulate in place, or (u, v, w) as b with
+    new o arrays for an Euler step u + dt * su."""
+    nx, ny, nz = _grid(u, halo)
+    ou, ov, ow = _out(u, ou), _out(u, ov), _out(u, ow)
+    _fields(u, v, w, bu, bv, bw, ou, ov, ow)
+    t1, t2 = _profile(tzc1, nz, u.device), _profile(tzc2, nz, u.device)
+    _check(lib.pw_advect_fwd_update(_ptr(u), _ptr(v), _ptr(w), _ptr(t1), _ptr(t2), float(tcx), float(tcy),
+                                    nx, ny, nz, halo, _ptr(bu), _ptr(bv), _ptr(bw), float(beta),
+                                    _ptr(ou), _ptr(ov), _ptr(ow), _dtype_code(u, compute), _stream()))
+    return ou, ov, ow
 
 
 def adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, halo, gu=None, gv=None, gw=None, compute=None):

@@ -29,6 +29,7 @@ def lib():
     L.pw_advect_fwd.argtypes = [vp] * 5 + [d, d] + [i] * 4 + [vp] * 3 + [i, vp]
     L.pw_advect_adj.argtypes = [vp] * 8 + [d, d] + [i] * 4 + [vp] * 3 + [i, vp]
     L.pw_advect_fwd_adj.argtypes = [vp] * 8 + [d, d] + [i] * 4 + [vp] * 6 + [i, vp]
+    L.pw_advect_fwd_update.argtypes = [vp] * 5 + [d, d] + [i] * 4 + [vp] * 3 + [d] + [vp] * 3 + [i, vp]
     L.pw_pad_periodic.argtypes = [vp, vp] + [i] * 5 + [vp]
     L.pw_halo_periodic.argtypes = [vp] + [i] * 5 + [vp]
     L.pw_fill_uniform.argtypes = [vp] + [i] * 4 + [ctypes.c_ulonglong, i, d, i, i, vp]
@@ -118,6 +119,30 @@ def test_adj_and_fused_checks(lib):
     rc = lib.pw_advect_fwd_adj(p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], -0.005, -0.005, *GRID,
                                None, p[9], p[10], p[11], p[12], p[13], 0, None)
     assert rc == PW_ERR_ARG
+
+
+def update(lib, p, b, o):
+    return lib.pw_advect_fwd_update(p[0], p[1], p[2], p[3], p[4], -0.005, -0.005, *GRID, b[0], b[1], b[2], 0.5,
+                                    o[0], o[1], o[2], 0, None)
+
+
+def test_update_checks(lib):
+    p, o = ADDR[:5], ADDR[8:11]
+    # a null or misaligned base array
+    assert update(lib, p, [None, ADDR[12], ADDR[13]], o) == PW_ERR_ARG
+    assert update(lib, p, [ADDR[11] + 4, ADDR[12], ADDR[13]], o) == PW_ERR_ALIGN
+    # bv is the output ou: only ov itself may be passed as bv
+    assert update(lib, p, [ADDR[11], o[0], ADDR[13]], o) == PW_ERR_ALIAS
+    assert b"bv overlaps output" in lib.pw_last_error()
+    # bw straddles ow
+    assert update(lib, p, [ADDR[11], ADDR[12], o[2] - 8], o) == PW_ERR_ALIAS
+    # an output over an input field is refused as for the plain forward
+    assert update(lib, p, list(p[:3]), [p[0], o[1], o[2]]) == PW_ERR_ALIAS
+    # accepted by the host-side checks: in place (b = o), Euler (b = u, v, w),
+    # separate arrays; they then fail only at the device query
+    for b in (list(o), list(p[:3]), ADDR[11:14]):
+        assert update(lib, p, b, o) == PW_ERR_ARG
+        assert b"device" in lib.pw_last_error()
 
 
 def test_host_pointer_rejected_without_launch(lib):

@@ -2,6 +2,8 @@
 pipelined slab transfer must reproduce the device-resident forward bit for
 bit, write only interior columns of the host outputs, and order itself on the
 caller's stream."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -26,12 +28,31 @@ def _host(arr, dtype, pinned):
     return t
 
 
-@pytest.mark.parametrize("pinned", [True, False], ids=["pinned", "pageable"])
+@pytest.fixture
+def copy_out_env():
+    """Sets PW_OFFLOAD_COPY_OUT for one test (the library reads it per call)."""
+    old = os.environ.get("PW_OFFLOAD_COPY_OUT")
+
+    def set_(runtime):
+        os.environ["PW_OFFLOAD_COPY_OUT"] = "runtime" if runtime else "kernel"
+    yield set_
+    if old is None:
+        os.environ.pop("PW_OFFLOAD_COPY_OUT", None)
+    else:
+        os.environ["PW_OFFLOAD_COPY_OUT"] = old
+
+
+# pinned outputs are written back by the library's copy kernel, or by the
+# runtime's copies when asked; pageable outputs always by the runtime
+@pytest.mark.parametrize("mode", ["pinned", "pinned_runtime_copy", "pageable"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("shape,chunks", [((20, 13, 64, 31), (1, 3, 7, 20, 64)),
-                                          ((9, 6, 7, 32), (4, 9))],
-                         ids=["20x13x64", "9x6x7"])
-def test_offload_matches_device_path(pw, shape, chunks, dtype, pinned):
+                                          ((9, 6, 7, 32), (4, 9)),
+                                          ((6, 5, 3, 34), (2, 5))],
+                         ids=["20x13x64", "9x6x7", "6x5x3"])
+def test_offload_matches_device_path(pw, copy_out_env, shape, chunks, dtype, mode):
+    pinned = mode != "pageable"
+    copy_out_env(mode == "pinned_runtime_copy")
     nx, ny, nz, seed = shape
     fields, _, coef = host_case(nx, ny, nz, seed)
     tzc1, tzc2, tcx, tcy = coef
@@ -41,7 +62,7 @@ def test_offload_matches_device_path(pw, shape, chunks, dtype, pinned):
     ref = [o.cpu() for o in pw.fwd(*dev_in, t1, t2, tcx, tcy, H)]
     host_in = [_host(a, dtype, pinned) for a in st]
     for chunk in chunks:
-        log("offload %s %s %s chunk %d" % (shape, dtype, "pinned" if pinned else "pageable", chunk))
+        log("offload %s %s %s chunk %d" % (shape, dtype, mode, chunk))
         outs = [torch.full(host_in[0].shape, float("nan"), dtype=dtype, pin_memory=pinned) for _ in range(3)]
         ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, H, dtype, chunk), dtype=torch.uint8,
                          device=DEV)
@@ -55,10 +76,13 @@ def test_offload_matches_device_path(pw, shape, chunks, dtype, pinned):
             assert np.all(np.isnan(g[:, :H])) and np.all(np.isnan(g[:, -H:]))  # y halo columns untouched
 
 
-def test_offload_orders_on_callers_stream(pw):
+@pytest.mark.parametrize("runtime_copy", [False, True], ids=["copy_kernel", "runtime_copy"])
+def test_offload_orders_on_callers_stream(pw, copy_out_env, runtime_copy):
     """Work queued on the stream before the call (a device fill of a tensor
     that is then copied into the pinned input) is seen by the offload, and
-    work queued after it sees the host results."""
+    work queued after it (a copy reading the pinned outputs) sees the host
+    results."""
+    copy_out_env(runtime_copy)
     nx, ny, nz, seed = 16, 12, 64, 33
     fields, _, coef = host_case(nx, ny, nz, seed)
     tzc1, tzc2, tcx, tcy = coef
