@@ -9,8 +9,9 @@ advection kernel.
 
 Printed: one JSON line with the headline value (FP64 fused fwd+adj Gcells/s),
 the roofline of that kernel (algorithmic bytes / measured average launch time
-against 8 TB/s HBM), per-path figures (fwd / adj / fused in FP64, FP32, and
-FP32 storage with FP64 arithmetic),
+against 8 TB/s HBM), per-path figures (fwd / adj / fused in FP64, FP32,
+FP32 storage with FP64 arithmetic, binary16 and bfloat16 storage; the fused
+Euler step and its unfused equivalent),
 and the CPU oracle timed on a bounded sample of the same workload.
 
 Also printed, as context: the host-resident offload (fields in pinned host
@@ -39,6 +40,7 @@ BYTES_PER_CELL = {  # algorithmic: each input read once, each output written onc
     # new fields (the same streams as the forward); unfused it is the forward
     # plus a pass reading u and su and writing the new field (+72 B FP64)
     ("update", 8): 48, ("update", 4): 24, ("fwd+axpy", 8): 120, ("fwd+axpy", 4): 60,
+    ("fwd", 2): 12, ("adj", 2): 18, ("fused", 2): 24,
 }
 DT = 0.5   # timestep of the update path (any value: the timing does not depend on it)
 
@@ -291,8 +293,9 @@ def main():
         return
     if args.only:
         path, dt = args.only.split(":")
-        g = Grid(pw, torch, nx, ny, nz, h, torch.float64 if dt == "f64" else torch.float32, seed,
-                 path != "fwd", compute=torch.float64 if dt == "f32f64" else None)
+        st_dt = {"f64": torch.float64, "f16": torch.float16, "bf16": torch.bfloat16}.get(dt, torch.float32)
+        g = Grid(pw, torch, nx, ny, nz, h, st_dt, seed, path != "fwd",
+                 compute=torch.float64 if dt == "f32f64" else None)
         torch.cuda.synchronize()
         for _ in range(args.warmup + args.steps):
             g.launch(pw, path)
@@ -341,8 +344,18 @@ def main():
             log("bench: %s f32-storage/f64-arithmetic %.2f ms" % (p, paths[p + "_f32f64"]["ms_avg"]))
         del g
         torch.cuda.empty_cache()
+        # 16-bit storage, float arithmetic
+        for tag, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            g = Grid(pw, torch, nx, ny, nz, h, dt, seed, True)
+            for p in ("fwd", "adj", "fused"):
+                g.launch(pw, p)
+                paths[p + "_" + tag] = path_record(p, 2, cells, time_launches(torch, lambda: g.launch(pw, p),
+                                                                               args.paths_reps))
+                log("bench: %s %s %.2f ms" % (p, tag, paths[p + "_" + tag]["ms_avg"]))
+            del g
+            torch.cuda.empty_cache()
         for p in ("fwd", "adj", "fused"):
-            for v in ("_f32", "_f32f64"):
+            for v in ("_f32", "_f32f64", "_f16", "_bf16"):
                 paths[p + v]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + v]["ms_avg"]
 
     kname = "fused_f64"

@@ -15,10 +15,12 @@
  * contiguous (section 3, Listings 3 and 4).  Interior cell (i, j, k) with
  * 0 <= i < nx, 0 <= j < ny, 0 <= k < nz is element
  *     ((i + halo) * (ny + 2*halo) + (j + halo)) * (nz + 2*halo) + (k + halo).
- * Element type: double for PW_F64, float for PW_F32 and PW_F32_F64.
+ * Element type: double for PW_F64, float for PW_F32 and PW_F32_F64, 16-bit
+ * for PW_F16 and PW_BF16.
  * tzc1, tzc2 are double arrays of length nz indexed by interior level k, for
- * every dtype (PW_F32 rounds them to float where it uses them).
- * tcx, tcy are passed by value as double (rounded to float by PW_F32 only).
+ * every dtype (dtypes with float arithmetic round them to float where they
+ * use them).  tcx, tcy are passed by value as double (rounded to float by the
+ * dtypes with float arithmetic).
  *
  * Every pointer is a device pointer (hipMalloc / torch device memory) owned by
  * the caller, except the host field arrays of pw_advect_fwd_host.  The library
@@ -68,12 +70,19 @@
 extern "C" {
 #endif
 
-/* Element type of the field arrays and arithmetic type of the scheme.
- * PW_F32_F64 stores fields as float but computes in double (operands are
- * widened exactly, each result is rounded to float once); it moves the bytes
- * of PW_F32 with the arithmetic of PW_F64.  The utility calls treat it as
- * float storage. */
-typedef enum { PW_F64 = 0, PW_F32 = 1, PW_F32_F64 = 2 } pw_dtype;
+/* Element type of the field arrays and arithmetic type of the scheme
+ * (storage / arithmetic):
+ *   PW_F64      double / double
+ *   PW_F32      float / float
+ *   PW_F32_F64  float / double: operands are widened exactly, each result is
+ *               rounded to float once; the bytes of PW_F32 with the
+ *               arithmetic of PW_F64
+ *   PW_F16      IEEE binary16 / float
+ *   PW_BF16     bfloat16 (upper half of a binary32) / float
+ * The 16-bit types halve the bytes of PW_F32 again; each result is rounded to
+ * the storage type once (round to nearest even).  The utility calls use the
+ * storage type only. */
+typedef enum { PW_F64 = 0, PW_F32 = 1, PW_F32_F64 = 2, PW_F16 = 3, PW_BF16 = 4 } pw_dtype;
 
 enum {
     PW_OK = 0,
@@ -210,8 +219,10 @@ int pw_pad_periodic(const void *interior, void *storage, int nx, int ny, int nz,
  * counter-based uniform of Steele, Lea and Flood (OOPSLA 2014) for seed
  * `seed`, stream `field_id` and counter = interior linear index
  * (i*ny + j)*nz + k:  z = mix(seed*256 + field_id + (counter+1)*0x9E3779B97F4A7C15),
- * t = ((z >> 11) - 2^52) * 2^-52, value = amp * t rounded once (to double,
- * then to float for PW_F32).  With zero_lids != 0 levels 0 and nz-1 are 0.
+ * t = ((z >> 11) - 2^52) * 2^-52, value = amp * t rounded to double, then to
+ * float for the float-storage dtypes, then to the 16-bit type for PW_F16 and
+ * PW_BF16 (each step rounds to nearest even).  With zero_lids != 0 levels 0
+ * and nz-1 are 0.
  * z-halo levels are set to 0; x/y halo columns are not written.
  */
 int pw_fill_uniform(void *storage, int nx, int ny, int nz, int halo,

@@ -10,6 +10,7 @@
 #include <cstring>
 
 #include "../../include/pwadvect.h"
+#include "pw_half.h"
 #include "pw_internal.h"
 
 namespace {
@@ -32,14 +33,30 @@ int ok()
     return PW_OK;
 }
 
-size_t elem_size(int dtype) { return dtype == PW_F64 ? 8 : 4; }
-bool storage_is_double(int dtype) { return dtype == PW_F64; }
+size_t elem_size(int dtype)
+{
+    return dtype == PW_F64 ? 8 : (dtype == PW_F16 || dtype == PW_BF16) ? 2 : 4;
+}
+
+// Calls f(T{}, C{}) with the storage type T and arithmetic type C of dtype
+// (which check_shape has validated).
+template <typename F>
+int with_types(int dtype, F&& f)
+{
+    switch (dtype) {
+    case PW_F64: return f(double{}, double{});
+    case PW_F32_F64: return f(float{}, double{});
+    case PW_F16: return f(_Float16{}, float{});
+    case PW_BF16: return f(bf16_t{}, float{});
+    default: return f(float{}, float{});
+    }
+}
 
 // Shape checks shared by every entry point; fills g and the byte count of
 // one storage array.
 int check_shape(int nx, int ny, int nz, int halo, int dtype, Geom& g, size_t& bytes)
 {
-    if (dtype != PW_F64 && dtype != PW_F32 && dtype != PW_F32_F64)
+    if (dtype != PW_F64 && dtype != PW_F32 && dtype != PW_F32_F64 && dtype != PW_F16 && dtype != PW_BF16)
         return fail(PW_ERR_ARG, "unknown dtype %d", dtype);
     if (nx < 1 || ny < 1) return fail(PW_ERR_ARG, "nx=%d, ny=%d: need nx >= 1 and ny >= 1", nx, ny);
     if (nz < 2) return fail(PW_ERR_ARG, "nz=%d: need nz >= 2", nz);
@@ -303,11 +320,10 @@ int pw_advect_fwd(const void* u, const void* v, const void* w, const double* tzc
     size_t bytes;
     int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
     if (rc) return rc;
-    if (dtype == PW_F64)
-        return do_fwd<double, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
-    if (dtype == PW_F32_F64)
-        return do_fwd<float, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
-    return do_fwd<float, float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, (hipStream_t)stream);
+    return with_types(dtype, [&](auto t, auto c) {
+        return do_fwd<decltype(t), decltype(c)>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw,
+                                                (hipStream_t)stream);
+    });
 }
 
 int pw_advect_fwd_update(const void* u, const void* v, const void* w, const double* tzc1, const double* tzc2,
@@ -320,14 +336,10 @@ int pw_advect_fwd_update(const void* u, const void* v, const void* w, const doub
     int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
     if (rc) return rc;
     const void* const base[3] = {bu, bv, bw};
-    if (dtype == PW_F64)
-        return do_fwd<double, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow, (hipStream_t)stream,
-                                      base, beta);
-    if (dtype == PW_F32_F64)
-        return do_fwd<float, double>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow, (hipStream_t)stream,
-                                     base, beta);
-    return do_fwd<float, float>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow, (hipStream_t)stream, base,
-                                beta);
+    return with_types(dtype, [&](auto t, auto c) {
+        return do_fwd<decltype(t), decltype(c)>(u, v, w, tzc1, tzc2, tcx, tcy, g, bytes, ou, ov, ow,
+                                                (hipStream_t)stream, base, beta);
+    });
 }
 
 int pw_advect_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
@@ -339,14 +351,10 @@ int pw_advect_adj(const void* u, const void* v, const void* w, const void* lu, c
     int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
     if (rc) return rc;
     if (!gu || !gv || !gw) return fail(PW_ERR_ARG, "gu, gv, gw must not be NULL");
-    if (dtype == PW_F64)
-        return do_adj<double, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr,
-                                      nullptr, gu, gv, gw, (hipStream_t)stream);
-    if (dtype == PW_F32_F64)
-        return do_adj<float, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr,
-                                     nullptr, gu, gv, gw, (hipStream_t)stream);
-    return do_adj<float, float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr, nullptr, nullptr,
-                                gu, gv, gw, (hipStream_t)stream);
+    return with_types(dtype, [&](auto t, auto c) {
+        return do_adj<decltype(t), decltype(c)>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, nullptr,
+                                                nullptr, nullptr, gu, gv, gw, (hipStream_t)stream);
+    });
 }
 
 int pw_advect_fwd_adj(const void* u, const void* v, const void* w, const void* lu, const void* lv,
@@ -360,14 +368,10 @@ int pw_advect_fwd_adj(const void* u, const void* v, const void* w, const void* l
     if (rc) return rc;
     if (!su || !sv || !sw) return fail(PW_ERR_ARG, "su, sv, sw must not be NULL");
     if (!gu || !gv || !gw) return fail(PW_ERR_ARG, "gu, gv, gw must not be NULL");
-    if (dtype == PW_F64)
-        return do_adj<double, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv,
-                                      gw, (hipStream_t)stream);
-    if (dtype == PW_F32_F64)
-        return do_adj<float, double>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv,
-                                     gw, (hipStream_t)stream);
-    return do_adj<float, float>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw, gu, gv, gw,
-                                (hipStream_t)stream);
+    return with_types(dtype, [&](auto t, auto c) {
+        return do_adj<decltype(t), decltype(c)>(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, g, bytes, su, sv, sw,
+                                                gu, gv, gw, (hipStream_t)stream);
+    });
 }
 
 size_t pw_offload_workspace_bytes(int nx, int ny, int nz, int halo, int dtype, int chunk)
@@ -413,7 +417,7 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
     Geom sg = g;
     sg.nx = chunk;
     const Arr ws[1] = {{workspace, need, 16, "workspace"}};
-    const int kern = storage_is_double(dtype) ? resolve_kernel<double>(sg, ws, 1) : resolve_kernel<float>(sg, ws, 1);
+    const int kern = with_types(dtype, [&](auto t, auto) { return resolve_kernel<decltype(t)>(sg, ws, 1); });
     if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz == 64");
     // mapped pinned outputs are written by a copy kernel unless
     // PW_OFFLOAD_COPY_OUT=runtime asks for the runtime's copies
@@ -422,26 +426,14 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
     bool mapped = !(env && std::strcmp(env, "runtime") == 0);
     for (int f = 0; f < 3 && mapped; ++f) mapped = (od[f] = mapped_host(out[f].p, bytes)) != nullptr;
     const char* what = "";
-    int e;
     const bool march = kern == PW_KERNEL_MARCH;
-    if (dtype == PW_F64) {
-        double* const o[3] = {(double*)od[0], (double*)od[1], (double*)od[2]};
-        e = offload_fwd<double, double>((const double*)u, (const double*)v, (const double*)w, tzc1, tzc2, tcx,
-                                        tcy, g, (double*)su, (double*)sv, (double*)sw, mapped ? o : nullptr, chunk,
-                                        workspace, march, (hipStream_t)stream, &what);
-    } else {
-        float* const o[3] = {(float*)od[0], (float*)od[1], (float*)od[2]};
-        if (dtype == PW_F32_F64)
-            e = offload_fwd<float, double>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx,
-                                           tcy, g, (float*)su, (float*)sv, (float*)sw,
-                                           mapped ? o : nullptr, chunk, workspace, march, (hipStream_t)stream,
-                                           &what);
-        else
-            e = offload_fwd<float, float>((const float*)u, (const float*)v, (const float*)w, tzc1, tzc2, tcx, tcy,
-                                          g, (float*)su, (float*)sv, (float*)sw,
-                                          mapped ? o : nullptr, chunk, workspace, march, (hipStream_t)stream,
-                                          &what);
-    }
+    const int e = with_types(dtype, [&](auto t, auto c) {
+        using T = decltype(t);
+        T* const o[3] = {(T*)od[0], (T*)od[1], (T*)od[2]};
+        return offload_fwd<T, decltype(c)>((const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, g, (T*)su,
+                                           (T*)sv, (T*)sw, mapped ? o : nullptr, chunk, workspace, march,
+                                           (hipStream_t)stream, &what);
+    });
     if (e) return fail(PW_ERR_HIP, "pw_advect_fwd_host: %s: %s", what, hipGetErrorString((hipError_t)e));
     return launched("pw_advect_fwd_host");
 }
@@ -455,10 +447,10 @@ int pw_halo_periodic(void* storage, int nx, int ny, int nz, int halo, int dtype,
     rc = check_one(storage, bytes, elem_size(dtype), "storage");
     if (rc) return rc;
     (void)hipGetLastError();
-    if (storage_is_double(dtype))
-        launch_halo_periodic<double>((double*)storage, g, (hipStream_t)stream);
-    else
-        launch_halo_periodic<float>((float*)storage, g, (hipStream_t)stream);
+    with_types(dtype, [&](auto t, auto) {
+        launch_halo_periodic<decltype(t)>((decltype(t)*)storage, g, (hipStream_t)stream);
+        return 0;
+    });
     return launched("pw_halo_periodic");
 }
 
@@ -478,10 +470,11 @@ int pw_pad_periodic(const void* interior, void* storage, int nx, int ny, int nz,
     rc = check_device(all, 2);
     if (rc) return rc;
     (void)hipGetLastError();
-    if (storage_is_double(dtype))
-        launch_pad_periodic<double>((const double*)interior, (double*)storage, g, (hipStream_t)stream);
-    else
-        launch_pad_periodic<float>((const float*)interior, (float*)storage, g, (hipStream_t)stream);
+    with_types(dtype, [&](auto t, auto) {
+        using T = decltype(t);
+        launch_pad_periodic<T>((const T*)interior, (T*)storage, g, (hipStream_t)stream);
+        return 0;
+    });
     return launched("pw_pad_periodic");
 }
 
@@ -496,10 +489,11 @@ int pw_fill_uniform(void* storage, int nx, int ny, int nz, int halo, unsigned lo
     rc = check_one(storage, bytes, elem_size(dtype), "storage");
     if (rc) return rc;
     (void)hipGetLastError();
-    if (storage_is_double(dtype))
-        launch_fill_uniform<double>((double*)storage, g, seed, field_id, amp, zero_lids, (hipStream_t)stream);
-    else
-        launch_fill_uniform<float>((float*)storage, g, seed, field_id, amp, zero_lids, (hipStream_t)stream);
+    with_types(dtype, [&](auto t, auto) {
+        launch_fill_uniform<decltype(t)>((decltype(t)*)storage, g, seed, field_id, amp, zero_lids,
+                                         (hipStream_t)stream);
+        return 0;
+    });
     return launched("pw_fill_uniform");
 }
 

@@ -7,6 +7,7 @@
 // the ny * Sz storage levels of the plane's interior columns, z fastest, so a
 // wavefront reads and writes contiguous runs of a column.  z-halo levels of
 // interior columns are written with 0.
+#include "pw_half.h"
 #include "pw_internal.h"
 #include "pw_stencil.h"
 
@@ -90,9 +91,9 @@ __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g
             sv = pw_update(bv, beta, sv);
             sw = pw_update(bw, beta, sw);
         }
-        a.su[b] = (T)su;
-        a.sv[b] = (T)sv;
-        a.sw[b] = (T)sw;
+        a.su[b] = store_round<T>(su);
+        a.sv[b] = store_round<T>(sv);
+        a.sw[b] = store_round<T>(sw);
     }
 }
 
@@ -127,15 +128,15 @@ __global__ void __launch_bounds__(kBlock) adj_direct_kernel(AdjArgs<T> a, Geom g
         if (FUSED) {
             C su, sv, sw;
             pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
-            a.su[b] = (T)su;
-            a.sv[b] = (T)sv;
-            a.sw[b] = (T)sw;
+            a.su[b] = store_round<T>(su);
+            a.sv[b] = store_round<T>(sv);
+            a.sw[b] = store_round<T>(sw);
         }
         C gu, gv, gw;
         pw_adj_cell(u, v, w, lu, lv, lw, cf, k, g.nz, gu, gv, gw);
-        a.gu[b] = (T)gu;
-        a.gv[b] = (T)gv;
-        a.gw[b] = (T)gw;
+        a.gu[b] = store_round<T>(gu);
+        a.gv[b] = store_round<T>(gv);
+        a.gw[b] = store_round<T>(gw);
     }
 }
 
@@ -172,6 +173,10 @@ void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
 template void launch_fwd_direct<double, double>(const FwdArgs<double>&, const Geom&, hipStream_t);
 template void launch_fwd_direct<float, float>(const FwdArgs<float>&, const Geom&, hipStream_t);
 template void launch_fwd_direct<float, double>(const FwdArgs<float>&, const Geom&, hipStream_t);
+template void launch_fwd_direct<_Float16, float>(const FwdArgs<_Float16>&, const Geom&, hipStream_t);
+template void launch_fwd_direct<bf16_t, float>(const FwdArgs<bf16_t>&, const Geom&, hipStream_t);
 template void launch_adj_direct<double, double>(const AdjArgs<double>&, const Geom&, hipStream_t);
 template void launch_adj_direct<float, float>(const AdjArgs<float>&, const Geom&, hipStream_t);
 template void launch_adj_direct<float, double>(const AdjArgs<float>&, const Geom&, hipStream_t);
+template void launch_adj_direct<_Float16, float>(const AdjArgs<_Float16>&, const Geom&, hipStream_t);
+template void launch_adj_direct<bf16_t, float>(const AdjArgs<bf16_t>&, const Geom&, hipStream_t);

@@ -30,6 +30,7 @@
 // the same L2.
 #include <cstdlib>
 
+#include "pw_half.h"
 #include "pw_internal.h"
 #include "pw_stencil.h"
 
@@ -66,6 +67,23 @@ __device__ __forceinline__ double lane_shift(double x)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+template <bool BELOW>
+__device__ __forceinline__ _Float16 lane_shift(_Float16 x)
+{
+    const int v = (int)__builtin_bit_cast(unsigned short, x);
+    const int r = BELOW ? dpp_from_below(v) : dpp_from_above(v);
+    return __builtin_bit_cast(_Float16, (unsigned short)r);
+}
+
+template <bool BELOW>
+__device__ __forceinline__ bf16_t lane_shift(bf16_t x)
+{
+    const int r = BELOW ? dpp_from_below((int)x.bits) : dpp_from_above((int)x.bits);
+    bf16_t y;
+    y.bits = (unsigned short)r;
+    return y;
+}
+
 template <typename T>
 __device__ __forceinline__ T below(T x) { return lane_shift<true>(x); }   // level k-1
 template <typename T>
@@ -99,6 +117,18 @@ __device__ __forceinline__ float buf_load<float>(rsrc_t r, unsigned off)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
+template <>
+__device__ __forceinline__ _Float16 buf_load<_Float16>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ bf16_t buf_load<bf16_t>(rsrc_t r, unsigned off)
+{
+    bf16_t y;
+    y.bits = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+    return y;
+}
 
 using u32x2 = unsigned int __attribute__((vector_size(8)));
 __device__ __forceinline__ void buf_store(double x, rsrc_t r, unsigned off)
@@ -108,6 +138,14 @@ __device__ __forceinline__ void buf_store(double x, rsrc_t r, unsigned off)
 __device__ __forceinline__ void buf_store(float x, rsrc_t r, unsigned off)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(_Float16 x, rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(bf16_t x, rsrc_t r, unsigned off)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(x.bits, r, (int)off, 0, 0);
 }
 
 template <typename T, int NF>
@@ -295,7 +333,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 const rsrc_t r = column_rsrc(column(dst, p, 0), stbytes);
                 C o = out[q];
                 if (UPD != 0 && q < 3) o = pw_update((C)R[UPD == 2 ? q : NF + q][rc], (C)a.beta, o);
-                buf_store((T)o, r, voff);
+                buf_store(store_round<T>(o), r, voff);
                 buf_store(T(0), r, vpad);
             }
 
@@ -367,7 +405,7 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 template <typename T, typename C, int NF>
 int default_variant()
 {
-    return (NF == 3 || (sizeof(T) == 4 && sizeof(C) == 4)) ? 2 : 0;
+    return (NF == 3 || sizeof(C) == 4) ? 2 : 0;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
@@ -449,6 +487,12 @@ void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
 
 template bool march_supported<double>(const Geom&);
 template bool march_supported<float>(const Geom&);
+template bool march_supported<_Float16>(const Geom&);
+template bool march_supported<bf16_t>(const Geom&);
+template void launch_fwd_march<_Float16, float>(const FwdArgs<_Float16>&, const Geom&, hipStream_t);
+template void launch_fwd_march<bf16_t, float>(const FwdArgs<bf16_t>&, const Geom&, hipStream_t);
+template void launch_adj_march<_Float16, float>(const AdjArgs<_Float16>&, const Geom&, hipStream_t);
+template void launch_adj_march<bf16_t, float>(const AdjArgs<bf16_t>&, const Geom&, hipStream_t);
 template void launch_fwd_march<double, double>(const FwdArgs<double>&, const Geom&, hipStream_t);
 template void launch_fwd_march<float, float>(const FwdArgs<float>&, const Geom&, hipStream_t);
 template void launch_fwd_march<float, double>(const FwdArgs<float>&, const Geom&, hipStream_t);

@@ -30,6 +30,7 @@
 #include <mutex>
 
 #include "../../include/pwadvect.h"
+#include "pw_half.h"
 #include "pw_internal.h"
 
 namespace {
@@ -208,4 +209,10 @@ template int offload_fwd<float, float>(const float*, const float*, const float*,
                                        hipStream_t, const char**);
 template int offload_fwd<float, double>(const float*, const float*, const float*, const double*, const double*,
                                         double, double, const Geom&, float*, float*, float*, float* const*, int,
+                                        void*, bool, hipStream_t, const char**);
+template int offload_fwd<_Float16, float>(const _Float16*, const _Float16*, const _Float16*, const double*,
+                                          const double*, double, double, const Geom&, _Float16*, _Float16*,
+                                          _Float16*, _Float16* const*, int, void*, bool, hipStream_t, const char**);
+template int offload_fwd<bf16_t, float>(const bf16_t*, const bf16_t*, const bf16_t*, const double*, const double*,
+                                        double, double, const Geom&, bf16_t*, bf16_t*, bf16_t*, bf16_t* const*, int,
                                         void*, bool, hipStream_t, const char**);

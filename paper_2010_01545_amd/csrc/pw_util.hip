@@ -1,5 +1,6 @@
 // pw_util.hip -- storage preparation kernels: periodic halo fill, padding of a
 // compact interior array, and the counter-based input generator.
+#include "pw_half.h"
 #include "pw_internal.h"
 
 namespace {
@@ -86,9 +87,9 @@ __global__ void __launch_bounds__(kBlock) fill_uniform_kernel(T* __restrict__ st
             const unsigned long long z = splitmix64_mix(state + (idx + 1ULL) * 0x9E3779B97F4A7C15ULL);
             const long long m = (long long)(z >> 11) - (1LL << 52);
             const double unit = (double)m * 0x1p-52;  // exact
-            val = amp * unit;                         // one rounding
+            val = amp * unit;                         // one rounding (then to_storage)
         }
-        st[(long long)(i + g.h) * g.sx + (long long)(j + g.h) * g.sy + kk] = (T)val;
+        st[(long long)(i + g.h) * g.sx + (long long)(j + g.h) * g.sy + kk] = to_storage<T>(val);
     }
 }
 
@@ -131,3 +132,11 @@ template void launch_fill_uniform<double>(double*, const Geom&, unsigned long lo
                                           hipStream_t);
 template void launch_fill_uniform<float>(float*, const Geom&, unsigned long long, int, double, int,
                                          hipStream_t);
+template void launch_halo_periodic<_Float16>(_Float16*, const Geom&, hipStream_t);
+template void launch_halo_periodic<bf16_t>(bf16_t*, const Geom&, hipStream_t);
+template void launch_pad_periodic<_Float16>(const _Float16*, _Float16*, const Geom&, hipStream_t);
+template void launch_pad_periodic<bf16_t>(const bf16_t*, bf16_t*, const Geom&, hipStream_t);
+template void launch_fill_uniform<_Float16>(_Float16*, const Geom&, unsigned long long, int, double, int,
+                                            hipStream_t);
+template void launch_fill_uniform<bf16_t>(bf16_t*, const Geom&, unsigned long long, int, double, int,
+                                          hipStream_t);

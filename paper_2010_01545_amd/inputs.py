@@ -126,6 +126,29 @@ def coefficients(nz, dx=50.0, dy=50.0, dz0=10.0, stretch=1.05):
 
 
 # The five workload shapes (x, y, z) and seeds.
+def round_storage(x, kind):
+    """Values of ``x`` (float64) as the library's storage type ``kind`` holds
+    them, returned as float64: "f64" unchanged; "f32" rounded to float;
+    "f16" / "bf16" rounded to float, then to IEEE binary16 / bfloat16 (each
+    step round-to-nearest-even, as the device generator defines it)."""
+    x = np.asarray(x, dtype=np.float64)
+    if kind == "f64":
+        return x.copy()
+    x32 = x.astype(np.float32)
+    if kind == "f32":
+        return x32.astype(np.float64)
+    if kind == "f16":
+        return x32.astype(np.float16).astype(np.float64)
+    if kind == "bf16":
+        b = x32.view(np.uint32).astype(np.uint64)
+        nan = np.isnan(x32)
+        r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+        out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+        out[nan] = np.nan
+        return out
+    raise ValueError(kind)
+
+
 WORKLOADS = {
     "small": dict(nx=32, ny=32, nz=64, seed=0),
     "medium": dict(nx=256, ny=256, nz=64, seed=1),

@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwadvect.so")
 
-PW_F64, PW_F32, PW_F32_F64 = 0, 1, 2
+PW_F64, PW_F32, PW_F32_F64, PW_F16, PW_BF16 = 0, 1, 2, 3, 4
 KERNELS = {"auto": 0, "direct": 1, "march": 2}
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
           -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
@@ -71,6 +71,10 @@ def _dtype_code(t, compute=None):
         return PW_F32
     if st == torch.float32 and compute == torch.float64:
         return PW_F32_F64
+    if st == torch.float16 and compute in (torch.float16, torch.float32):
+        return PW_F16      # 16-bit storage is always computed in float
+    if st == torch.bfloat16 and compute in (torch.bfloat16, torch.float32):
+        return PW_BF16
     raise TypeError("unsupported storage/compute dtypes %s/%s" % (st, compute))
 
 

@@ -20,8 +20,11 @@ def pw():
     return pwadvect
 
 
+KINDS = {torch.float64: "f64", torch.float32: "f32", torch.float16: "f16", torch.bfloat16: "bf16"}
+
+
 @pytest.mark.parametrize("shape", [(8, 6, 64), (5, 3, 7), (1, 1, 2)])
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("dtype", list(KINDS), ids=list(KINDS.values()))
 def test_fill_uniform_matches_host_generator(pw, shape, dtype):
     nx, ny, nz = shape
     log("fill %s %s" % (shape, dtype))
@@ -29,12 +32,24 @@ def test_fill_uniform_matches_host_generator(pw, shape, dtype):
                            (inputs.FIELD_LV, 1.0, False)):
         st = torch.full((nx + 2 * H, ny + 2 * H, nz + 2 * H), float("nan"), dtype=dtype, device=DEV)
         pw.fill_uniform(st, H, 7, fid, amp, lids)
-        got = st.cpu().numpy()
-        ref = inputs.uniform_field(7, fid, nx, ny, nz, amp=amp, zero_lids=lids)
-        assert np.array_equal(oracle.interior(got, H), ref.astype(got.dtype))
+        got = st.cpu().double().numpy()
+        ref = inputs.round_storage(inputs.uniform_field(7, fid, nx, ny, nz, amp=amp, zero_lids=lids), KINDS[dtype])
+        assert np.array_equal(oracle.interior(got, H), ref)
         cols = got[H:-H, H:-H]
         assert np.all(cols[:, :, :H] == 0) and np.all(cols[:, :, -H:] == 0)
         assert np.all(np.isnan(got[:H])) and np.all(np.isnan(got[:, -H:]))
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
+def test_pad_and_halo_16bit(pw, dtype):
+    """The pad and halo kernels move 16-bit elements unchanged."""
+    x = inputs.round_storage(np.random.default_rng(2).standard_normal((5, 4, 7)), KINDS[dtype])
+    ref = oracle.pad_periodic(x, H)
+    got = pw.pad_periodic(torch.from_numpy(x).to(DEV, dtype), H)
+    assert np.array_equal(got.cpu().double().numpy(), ref)
+    got[:H] = 3.0
+    pw.halo_periodic(got, H)
+    assert np.array_equal(got.cpu().double().numpy(), ref)
 
 
 @pytest.mark.parametrize("shape", [(8, 6, 64), (5, 3, 7), (1, 1, 2), (2, 5, 3)])

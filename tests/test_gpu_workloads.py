@@ -2,8 +2,10 @@
 times (kernel selection "auto").
 
 * 256x256x64 (seed 1): full-grid FP64 forward parity.
-* 1024x1024x64 (seed 2, smooth u component): FP64 and FP32 forward against
-  the FP64 oracle on the original FP64 inputs; max and RMS error per field.
+* 1024x1024x64 (seed 2, smooth u component): forward in every dtype (FP64,
+  FP32, FP32 storage with FP64 arithmetic, binary16 and bfloat16 storage)
+  against the FP64 oracle on the original FP64 inputs; max and RMS error per
+  field.
 * 512x512x64 (seed 3): differentiation -- torch.autograd through the library
   against the oracle adjoint, central differences on 64 random cells, the
   tangent-linear dot-product test and the Euler identity.
@@ -97,6 +99,30 @@ def test_precision_1024(pw):
             "rms_rel": rms_rel(gi, r), "max_over_T": float(np.max(np.abs(gi - r) / np.maximum(t, 1e-300)))}
         assert np.all(np.abs(gi - r) <= 24 * 2.0 ** -24 * t + 1e-30), name
         assert normwise(gi, r) <= 1e-5, name
+    del got32
+    # FP32 storage with FP64 arithmetic: only the input and output roundings
+    gotm = pw.fwd(*dev_storage(pw, f32, torch.float32), *coef_dev(coef), H, compute=torch.float64)
+    for name, g, r, t in zip(("su", "sv", "sw"), gotm, ref, mag):
+        gi = inner(g).cpu().numpy().astype(np.float64)
+        rec["fields"][name]["f32_f64"] = {
+            "max_abs": float(np.max(np.abs(gi - r))), "max_rel": normwise(gi, r),
+            "rms_rel": rms_rel(gi, r), "max_over_T": float(np.max(np.abs(gi - r) / np.maximum(t, 1e-300)))}
+        assert np.all(np.abs(gi - r) <= 4 * 2.0 ** -24 * t + 2.0 ** -24 * np.abs(r) + 1e-30), name
+    del gotm
+    # 16-bit storage, float arithmetic: input rounding (u16 per input, about
+    # 3 u16 per product), the float arithmetic and one rounding of the result
+    for kind, dtype, u16, sub in (("f16", torch.float16, 2.0 ** -11, 2.0 ** -25),
+                                  ("bf16", torch.bfloat16, 2.0 ** -8, 0.0)):
+        f16 = [inputs.round_storage(a, kind) for a in fields]
+        got16 = pw.fwd(*dev_storage(pw, f16, dtype), *coef_dev(coef), H)
+        for name, g, r, t in zip(("su", "sv", "sw"), got16, ref, mag):
+            gi = inner(g).cpu().double().numpy()
+            rec["fields"][name][kind] = {
+                "max_abs": float(np.max(np.abs(gi - r))), "max_rel": normwise(gi, r),
+                "rms_rel": rms_rel(gi, r), "max_over_T": float(np.max(np.abs(gi - r) / np.maximum(t, 1e-300)))}
+            bound = (4 * u16 + 24 * 2.0 ** -24) * t + u16 * np.abs(r) + sub + 1e-30
+            assert np.all(np.abs(gi - r) <= bound), (kind, name)
+        del got16
     _report("precision_1024.json", rec)
     log(json.dumps(rec))
 
