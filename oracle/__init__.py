@@ -17,33 +17,56 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _libs = {}
+_override = []   # a library that replaces both builds (see use_library)
 
 _D = ctypes.POINTER(ctypes.c_double)
 
 
+def _configure(lib):
+    fwd_args = [_D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, _D]
+    lib.pw_oracle_fwd.argtypes = fwd_args
+    lib.pw_oracle_fwd.restype = None
+    lib.pw_oracle_fwd_abs.argtypes = fwd_args
+    lib.pw_oracle_fwd_abs.restype = None
+    lib.pw_oracle_adj.argtypes = [_D] * 8 + [ctypes.c_double, ctypes.c_double] + \
+        [ctypes.c_int] * 4 + [_D, _D, _D]
+    lib.pw_oracle_adj.restype = None
+    lib.pw_oracle_adj_abs.argtypes = lib.pw_oracle_adj.argtypes
+    lib.pw_oracle_adj_abs.restype = None
+    lib.pw_oracle_fold_periodic.argtypes = [_D] + [ctypes.c_int] * 4
+    lib.pw_oracle_fold_periodic.restype = None
+    return lib
+
+
 def _load(threaded=False):
+    if _override:
+        return _override[-1]
     name = "libpworacle_omp.so" if threaded else "libpworacle.so"
     if name not in _libs:
         path = os.path.join(HERE, name)
         if not os.path.exists(path):
             from .build import build_oracle
             build_oracle()
-        lib = ctypes.CDLL(path)
-        fwd_args = [_D, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
-                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D, _D]
-        lib.pw_oracle_fwd.argtypes = fwd_args
-        lib.pw_oracle_fwd.restype = None
-        lib.pw_oracle_fwd_abs.argtypes = fwd_args
-        lib.pw_oracle_fwd_abs.restype = None
-        lib.pw_oracle_adj.argtypes = [_D] * 8 + [ctypes.c_double, ctypes.c_double] + \
-            [ctypes.c_int] * 4 + [_D, _D, _D]
-        lib.pw_oracle_adj.restype = None
-        lib.pw_oracle_adj_abs.argtypes = lib.pw_oracle_adj.argtypes
-        lib.pw_oracle_adj_abs.restype = None
-        lib.pw_oracle_fold_periodic.argtypes = [_D] + [ctypes.c_int] * 4
-        lib.pw_oracle_fold_periodic.restype = None
-        _libs[name] = lib
+        _libs[name] = _configure(ctypes.CDLL(path))
     return _libs[name]
+
+
+class use_library:
+    """Context manager: route every oracle call to the shared library at
+    ``path`` (a build of a modified pw_oracle.c), for the mutation tests that
+    check the pins catch planted mistakes."""
+
+    def __init__(self, path):
+        self.lib = _configure(ctypes.CDLL(path))
+
+    def __enter__(self):
+        _override.append(self.lib)
+        return self
+
+    def __exit__(self, *exc):
+        _override.pop()
+        return False
 
 
 def _p(a):

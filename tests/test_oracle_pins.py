@@ -197,6 +197,27 @@ def test_pw_energy_conservation(oracle):
     assert abs(np.sum(w2 * sw2)) > 1e-6 * np.sum(np.abs(w2) * tw2)
 
 
+def test_z_halo_is_never_read(oracle):
+    """The scheme reads only interior levels (Listing 1 runs k over the column
+    and the top level drops the term that would reach above it): NaN in every
+    z-halo level of every input changes no interior result."""
+    nx, ny, nz = 6, 5, 7
+    coef = _coef(nz)
+    u, v, w = _random(25, nx, ny, nz)
+    lams = inputs.normal_fields(26, nx, ny, nz)
+    st = [oracle.pad_periodic(f, H) for f in (u, v, w)]
+    sl = [oracle.pad_periodic(f, H) for f in lams]
+    ref_s = oracle.fwd(*st, *coef, H)
+    ref_g = oracle.adj(*st, *sl, *coef, H)
+    for a in st + sl:
+        a[:, :, :H] = np.nan
+        a[:, :, -H:] = np.nan
+    got_s = oracle.fwd(*st, *coef, H)
+    got_g = oracle.adj(*st, *sl, *coef, H)
+    for x, y in zip(got_s + got_g, ref_s + ref_g):
+        assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
+
+
 # ------------------------------------------------------------ coefficients and generator
 def test_coefficient_profiles():
     tz1, tz2, tcx, tcy = inputs.coefficients(64)
