@@ -148,6 +148,56 @@ __device__ __forceinline__ void buf_store(bf16_t x, rsrc_t r, unsigned off)
     __builtin_amdgcn_raw_buffer_store_b16(x.bits, r, (int)off, 0, 0);
 }
 
+// Working type of the register ring, the LDS ring and the DPP shifts: the
+// storage type, except that 16-bit storage works in float.  A 16-bit load
+// lands in a float-typed register as raw bits (zero-extended) and becomes a
+// value where the plane is first used, so the conversion does not force a
+// wait on the prefetch; the raw pattern 0 (zero records, masks) widens to +0.
+template <typename T>
+struct Work {
+    using type = T;
+};
+template <>
+struct Work<_Float16> {
+    using type = float;
+};
+template <>
+struct Work<bf16_t> {
+    using type = float;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Work<T>::type ld_raw(rsrc_t r, unsigned off)
+{
+    return buf_load<T>(r, off);
+}
+template <>
+__device__ __forceinline__ float ld_raw<_Float16>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float ld_raw<bf16_t>(rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ typename Work<T>::type widen(typename Work<T>::type x)
+{
+    return x;
+}
+template <>
+__device__ __forceinline__ float widen<_Float16>(float x)
+{
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_bit_cast(unsigned, x));
+}
+template <>
+__device__ __forceinline__ float widen<bf16_t>(float x)
+{
+    return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, x) << 16);
+}
+
 template <typename T, int NF>
 struct MarchArgs {
     const T* in[NF];   // u, v, w [, lu, lv, lw]
@@ -176,8 +226,9 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
     constexpr int U = D + 3;        // register ring length
     constexpr int NR = NF + (UPD == 1 ? 3 : 0);   // ring rows: fields, then base arrays
-    __shared__ T s_uw[2 * NT][2][NCOL][NZ];
-    __shared__ T s_v[NT][3][NCOL][NZ];
+    using W = typename Work<T>::type;
+    __shared__ W s_uw[2 * NT][2][NCOL][NZ];
+    __shared__ W s_v[NT][3][NCOL][NZ];
 
     // the wave index is uniform over a wavefront: keep it (and every address
     // part derived from it) in scalar registers, so that a global access is a
@@ -220,26 +271,40 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     // 0).  The mask is applied where a freshly loaded plane is first used, so
     // that the prefetch is not waited for at the load.
     const bool live_uv = lam_uv_live(lane, NZ), live_w = lam_w_live(lane, NZ);
-    auto mask = [&](int f, T x) -> T {
+    auto mask = [&](int f, W x) -> W {
         if (f < 3 || f >= NF) return x;
-        return ((f == 5) ? live_w : live_uv) ? x : T(0);
+        return ((f == 5) ? live_w : live_uv) ? x : W(0);
     };
-    auto ld = [&](int f, int p, int dj, int bytes) -> T {
+    auto ld = [&](int f, int p, int dj, int bytes) -> W {   // raw for 16-bit storage
         const T* src = f < NF ? a.in[f] : a.b[f - NF];
-        return buf_load<T>(column_rsrc(column(src, p, dj), bytes), voff);
+        return ld_raw<T>(column_rsrc(column(src, p, dj), bytes), voff);
+    };
+    // Planes a segment uses: i0-1 .. i1 of the fields, i0 .. i1-1 of base
+    // arrays.  The ring is filled further ahead than that near the segment's
+    // end; those loads get a zero record count and read no memory.
+    auto ring_bytes = [&](int f, int pl) -> int {
+        const bool used = f < NF ? pl <= i1 : (pl >= i0 && pl < i1);
+        return used ? ldbytes : 0;
     };
 
-    T R[NR][U];
+    // Ring planes become values (widened, masked) where they are first used:
+    // u/w-type plane q in step q-1 (as x+1 and LDS deposit), v-type plane q in
+    // step q-2 (LDS deposit).  The fill does the planes first used before the
+    // loop: i0-1, i0 and, for v-type, i0+1.
+    W R[NR][U];
 #pragma unroll
     for (int f = 0; f < NR; ++f)
 #pragma unroll
-        for (int t = 0; t < D + 2; ++t) R[f][t] = mask(f, ld(f, i0 - 1 + t, 0, ldbytes));
-    T carry[NF];
+        for (int t = 0; t < D + 2; ++t) {
+            const W x = ld(f, i0 - 1 + t, 0, ring_bytes(f, i0 - 1 + t));
+            R[f][t] = (f < NF && t < (f % 3 == 1 ? 3 : 2)) ? mask(f, widen<T>(x)) : x;
+        }
+    W carry[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        if (f % 3 == 0) carry[f] = mask(f, ld(f, i0 - 1, 1, stbytes));   // F(i0-1, j+1)
-        else if (f % 3 == 1) carry[f] = mask(f, ld(f, i0, -1, stbytes)); // F(i0, j-1)
-        else carry[f] = T(0);
+        if (f % 3 == 0) carry[f] = mask(f, widen<T>(ld(f, i0 - 1, 1, stbytes)));   // F(i0-1, j+1)
+        else if (f % 3 == 1) carry[f] = mask(f, widen<T>(ld(f, i0, -1, stbytes))); // F(i0, j-1)
+        else carry[f] = W(0);
     }
     const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, lane, NZ);
 
@@ -270,22 +335,22 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 
             // prefetch plane p + D + 1
 #pragma unroll
-            for (int f = 0; f < NR; ++f) R[f][rnew] = ld(f, p + D + 1, 0, ldbytes);
+            for (int f = 0; f < NR; ++f) R[f][rnew] = ld(f, p + D + 1, 0, ring_bytes(f, p + D + 1));
 
-            // first use of planes p+1 (all fields) and p+2 (v-type deposit)
+            // first use of plane p+1 (u/w-type) and p+2 (v-type deposit)
 #pragma unroll
-            for (int f = 3; f < NF; ++f) {
-                R[f][rq0] = mask(f, R[f][rq0]);
-                if (f % 3 == 1) R[f][rq1] = mask(f, R[f][rq1]);
+            for (int f = 0; f < NF; ++f) {
+                if (f % 3 == 1) R[f][rq1] = mask(f, widen<T>(R[f][rq1]));
+                else R[f][rq0] = mask(f, widen<T>(R[f][rq0]));
             }
 
             C out[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
             if (comp) {  // arithmetic only: no memory access inside the branch
-                Star<T> st[NF];
+                Star<W> st[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     const int t = f / 3;
-                    Star<T>& q = st[f];
+                    Star<W>& q = st[f];
                     q.c = R[f][rc];
                     q.xm = R[f][rm];
                     q.xp = R[f][rq0];
@@ -311,7 +376,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 Star<C> sc[NF];  // operands in the arithmetic type
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const Star<T>& q = st[f];
+                    const Star<W>& q = st[f];
                     sc[f] = Star<C>{(C)q.c, (C)q.xm, (C)q.xp, (C)q.ym, (C)q.yp, (C)q.zm, (C)q.zp, (C)q.d1, (C)q.d2};
                 }
                 if (WS) pw_fwd_cell(sc[0], sc[1], sc[2], cf, lane, NZ, out[0], out[1], out[2]);
@@ -332,7 +397,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 T* const dst = q < 3 ? a.s[q] : a.gr[q - 3];
                 const rsrc_t r = column_rsrc(column(dst, p, 0), stbytes);
                 C o = out[q];
-                if (UPD != 0 && q < 3) o = pw_update((C)R[UPD == 2 ? q : NF + q][rc], (C)a.beta, o);
+                if (UPD == 1 && q < 3) o = pw_update((C)widen<T>(R[NF + q][rc]), (C)a.beta, o);
+                if (UPD == 2 && q < 3) o = pw_update((C)R[q][rc], (C)a.beta, o);
                 buf_store(store_round<T>(o), r, voff);
                 buf_store(T(0), r, vpad);
             }
@@ -382,7 +448,7 @@ constexpr int kD[kVariants] = {2, 4, 2, 4};
 template <typename T, int NF, int TY>
 constexpr int lds_bytes()
 {
-    return (int)sizeof(T) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
+    return (int)sizeof(typename Work<T>::type) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD>
