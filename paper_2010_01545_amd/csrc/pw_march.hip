@@ -29,6 +29,7 @@
 // strips, so the halo columns shared by neighbouring strips are read through
 // the same L2.
 #include <cstdlib>
+#include <type_traits>
 
 #include "pw_half.h"
 #include "pw_internal.h"
@@ -149,53 +150,41 @@ __device__ __forceinline__ void buf_store(bf16_t x, rsrc_t r, unsigned off)
 }
 
 // Working type of the register ring, the LDS ring and the DPP shifts: the
-// storage type, except that 16-bit storage works in float.  A 16-bit load
-// lands in a float-typed register as raw bits (zero-extended) and becomes a
-// value where the plane is first used, so the conversion does not force a
-// wait on the prefetch; the raw pattern 0 (zero records, masks) widens to +0.
-template <typename T>
-struct Work {
-    using type = T;
-};
-template <>
-struct Work<_Float16> {
-    using type = float;
-};
-template <>
-struct Work<bf16_t> {
-    using type = float;
-};
+// arithmetic type C when the storage type T is narrower (16-bit storage
+// works in float, float storage with FP64 arithmetic in double), else T.  A
+// narrow load lands in a W-typed register as raw bits (zero-extended) and
+// becomes a value where the plane is first used, so the conversion does not
+// force a wait on the prefetch; the raw pattern 0 (zero records, masks)
+// widens to +0.
+template <typename T, typename C>
+using work_t = typename std::conditional<(sizeof(T) < sizeof(C)), C, T>::type;
 
-template <typename T>
-__device__ __forceinline__ typename Work<T>::type ld_raw(rsrc_t r, unsigned off)
+template <typename T, typename W>
+__device__ __forceinline__ W ld_raw(rsrc_t r, unsigned off)
 {
-    return buf_load<T>(r, off);
-}
-template <>
-__device__ __forceinline__ float ld_raw<_Float16>(rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(float, (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
-}
-template <>
-__device__ __forceinline__ float ld_raw<bf16_t>(rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(float, (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+    if constexpr (sizeof(T) == sizeof(W)) {
+        return buf_load<T>(r, off);
+    } else if constexpr (sizeof(T) == 2) {
+        static_assert(sizeof(W) == 4, "16-bit storage works in float");
+        return __builtin_bit_cast(W, (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+    } else {
+        static_assert(sizeof(T) == 4 && sizeof(W) == 8, "float storage works in double");
+        return __builtin_bit_cast(W, (unsigned long long)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    }
 }
 
-template <typename T>
-__device__ __forceinline__ typename Work<T>::type widen(typename Work<T>::type x)
+template <typename T, typename W>
+__device__ __forceinline__ W widen(W x)
 {
-    return x;
-}
-template <>
-__device__ __forceinline__ float widen<_Float16>(float x)
-{
-    return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_bit_cast(unsigned, x));
-}
-template <>
-__device__ __forceinline__ float widen<bf16_t>(float x)
-{
-    return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, x) << 16);
+    if constexpr (sizeof(T) == sizeof(W)) {
+        return x;
+    } else if constexpr (std::is_same<T, bf16_t>::value) {
+        return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, x) << 16);
+    } else if constexpr (sizeof(T) == 2) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_bit_cast(unsigned, x));
+    } else {
+        return (double)__builtin_bit_cast(float, (unsigned)__builtin_bit_cast(unsigned long long, x));
+    }
 }
 
 template <typename T, int NF>
@@ -226,7 +215,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
     constexpr int U = D + 3;        // register ring length
     constexpr int NR = NF + (UPD == 1 ? 3 : 0);   // ring rows: fields, then base arrays
-    using W = typename Work<T>::type;
+    using W = work_t<T, C>;
     __shared__ W s_uw[2 * NT][2][NCOL][NZ];
     __shared__ W s_v[NT][3][NCOL][NZ];
 
@@ -277,7 +266,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     };
     auto ld = [&](int f, int p, int dj, int bytes) -> W {   // raw for 16-bit storage
         const T* src = f < NF ? a.in[f] : a.b[f - NF];
-        return ld_raw<T>(column_rsrc(column(src, p, dj), bytes), voff);
+        return ld_raw<T, W>(column_rsrc(column(src, p, dj), bytes), voff);
     };
     // Planes a segment uses: i0-1 .. i1 of the fields, i0 .. i1-1 of base
     // arrays.  The ring is filled further ahead than that near the segment's
@@ -297,13 +286,13 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 #pragma unroll
         for (int t = 0; t < D + 2; ++t) {
             const W x = ld(f, i0 - 1 + t, 0, ring_bytes(f, i0 - 1 + t));
-            R[f][t] = (f < NF && t < (f % 3 == 1 ? 3 : 2)) ? mask(f, widen<T>(x)) : x;
+            R[f][t] = (f < NF && t < (f % 3 == 1 ? 3 : 2)) ? mask(f, widen<T, W>(x)) : x;
         }
     W carry[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        if (f % 3 == 0) carry[f] = mask(f, widen<T>(ld(f, i0 - 1, 1, stbytes)));   // F(i0-1, j+1)
-        else if (f % 3 == 1) carry[f] = mask(f, widen<T>(ld(f, i0, -1, stbytes))); // F(i0, j-1)
+        if (f % 3 == 0) carry[f] = mask(f, widen<T, W>(ld(f, i0 - 1, 1, stbytes)));   // F(i0-1, j+1)
+        else if (f % 3 == 1) carry[f] = mask(f, widen<T, W>(ld(f, i0, -1, stbytes))); // F(i0, j-1)
         else carry[f] = W(0);
     }
     const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, lane, NZ);
@@ -340,8 +329,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
             // first use of plane p+1 (u/w-type) and p+2 (v-type deposit)
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                if (f % 3 == 1) R[f][rq1] = mask(f, widen<T>(R[f][rq1]));
-                else R[f][rq0] = mask(f, widen<T>(R[f][rq0]));
+                if (f % 3 == 1) R[f][rq1] = mask(f, widen<T, W>(R[f][rq1]));
+                else R[f][rq0] = mask(f, widen<T, W>(R[f][rq0]));
             }
 
             C out[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
@@ -397,7 +386,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 T* const dst = q < 3 ? a.s[q] : a.gr[q - 3];
                 const rsrc_t r = column_rsrc(column(dst, p, 0), stbytes);
                 C o = out[q];
-                if (UPD == 1 && q < 3) o = pw_update((C)widen<T>(R[NF + q][rc]), (C)a.beta, o);
+                if (UPD == 1 && q < 3) o = pw_update((C)widen<T, W>(R[NF + q][rc]), (C)a.beta, o);
                 if (UPD == 2 && q < 3) o = pw_update((C)R[q][rc], (C)a.beta, o);
                 buf_store(store_round<T>(o), r, voff);
                 buf_store(T(0), r, vpad);
@@ -445,16 +434,16 @@ constexpr int kVariants = 4;
 constexpr int kTY[kVariants] = {6, 6, 14, 14};
 constexpr int kD[kVariants] = {2, 4, 2, 4};
 
-template <typename T, int NF, int TY>
+template <typename T, typename C, int NF, int TY>
 constexpr int lds_bytes()
 {
-    return (int)sizeof(typename Work<T>::type) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
+    return (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD>
 void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
-    if constexpr (lds_bytes<T, NF, TY>() <= 65536) {
+    if constexpr (lds_bytes<T, C, NF, TY>() <= 65536) {
         const Launch l = plan(g, TY);
         hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, UPD>), dim3(l.grid), dim3(64 * (TY + 2)), 0,
                            s, m, g, l.LX, l.nstrips, l.nblocks);
