@@ -135,6 +135,7 @@ def path_record(path, esize, cells, times_ms):
     return {
         "gcells_per_s": cells / (avg * 1e-3) / 1e9,
         "ms_avg": avg, "ms_min": ts[0], "ms_median": ts[len(ts) // 2],
+        "ms_p90": ts[min(len(ts) - 1, int(0.9 * len(ts)))],
         "alg_bytes_per_cell": bpc,
         "alg_GBps": bpc * cells / (avg * 1e-3) / 1e9,
         "hbm_frac": bpc * cells / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -166,11 +167,19 @@ def cpu_baseline(nx, ny, nz, seed, budget_s=12.0, planes=32):
         spent += time.perf_counter() - t0
         reps += 1
     fused = cells * reps / spent / 1e9
-    # the forward alone with the OpenMP build of the same source
-    threads = os.cpu_count() or 1
+    # the forward alone with the OpenMP build of the same source; its thread
+    # count is OMP_NUM_THREADS when set, else one per usable core
+    usable = os.cpu_count() or 1
     try:
-        threads = len(os.sched_getaffinity(0))
+        usable = len(os.sched_getaffinity(0))
     except AttributeError:
+        pass
+    threads = int(os.environ.get("OMP_NUM_THREADS", usable))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
         pass
     t0 = time.perf_counter()
     nrep = 0
@@ -185,6 +194,7 @@ def cpu_baseline(nx, ny, nz, seed, budget_s=12.0, planes=32):
                   % (planes - 1, nx, ny, nz, cells, reps, spent),
         "fwd_openmp": {"value": fwd_omp, "unit": "Gcells/s", "threads": threads,
                        "sample": "oracle forward, OpenMP build, same slab"},
+        "host": {"cpu_model": model, "usable_cores": usable},
     }
 
 
@@ -370,6 +380,22 @@ def main():
             for v in ("_f32", "_f32f64", "_f16", "_bf16"):
                 paths[p + v]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + v]["ms_avg"]
 
+    # achievable-bandwidth reference: torch's device copy (__amd_rocclr_copyBuffer)
+    # of the same storage arrays, 6 reads + 6 writes (the fused kernel's
+    # streams) and 3 + 3 (the forward's)
+    g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True)
+    storage_bytes = g.f[0].numel() * 8
+    copy_ref = {"kernel": "torch copy_ of %d-byte storage arrays" % storage_bytes}
+    for tag, src, dst in (("6R6W", g.f + g.l, g.s + g.g), ("3R3W", g.f, g.s)):
+        step = lambda: [d.copy_(x) for d, x in zip(dst, src)]
+        step()
+        t = time_launches(torch, step, 5)
+        ms = sum(t) / len(t)
+        copy_ref[tag] = {"ms": ms, "GBps": 2 * len(src) * storage_bytes / (ms * 1e-3) / 1e9}
+    del g
+    torch.cuda.empty_cache()
+    log("bench: copy reference 6R6W %.0f GB/s, 3R3W %.0f GB/s" % (copy_ref["6R6W"]["GBps"], copy_ref["3R3W"]["GBps"]))
+
     kname = "fused_f64"
     traffic = measured_traffic(kname, args.workload)
     achieved = head["alg_GBps"]
@@ -390,6 +416,7 @@ def main():
                    "cells": cells, "kernel": args.kernel},
         "roofline": roofline,
         "paths": paths,
+        "copy_reference": copy_ref,
         "source_hash": kernel_source_hash(),
     }
     if not args.no_offload:
