@@ -78,6 +78,23 @@ def test_rejects_bad_dtype(lib):
     assert fwd(lib, dtype=7) == PW_ERR_ARG
 
 
+def test_dtype_codes(lib):
+    """PW_F64..PW_BF16 (0..4) pass the dtype check; the element size follows
+    the storage type (8, 4, 4, 2, 2 bytes) in the alignment and overlap checks."""
+    assert fwd(lib, dtype=5) == PW_ERR_ARG and b"dtype" in lib.pw_last_error()
+    assert fwd(lib, dtype=-1) == PW_ERR_ARG
+    cells = STORAGE // 8
+    for dtype, es in ((0, 8), (1, 4), (2, 4), (3, 2), (4, 2)):
+        p = list(ADDR[:8])
+        p[5] += es // 2 if es > 2 else 1      # su misaligned for its element type
+        assert fwd(lib, p, dtype=dtype) == PW_ERR_ALIGN, dtype
+        p = list(ADDR[:8])
+        p[6] = p[5] + cells * es - es         # sv starts on su's last element
+        assert fwd(lib, p, dtype=dtype) == PW_ERR_ALIAS, dtype
+        p[6] = p[5] + cells * es              # sv starts right after su
+        assert fwd(lib, p, dtype=dtype) not in (PW_ERR_ALIAS, PW_ERR_ALIGN), dtype
+
+
 def test_rejects_size_overflow(lib):
     assert fwd(lib, grid=(2 ** 31 - 3, 6, 64, 2)) == PW_ERR_SIZE
     assert fwd(lib, grid=(8, 2 ** 30, 64, 2)) == PW_ERR_SIZE
