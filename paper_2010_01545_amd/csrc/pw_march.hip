@@ -428,11 +428,15 @@ Launch plan(const Geom& g, int TY)
     return l;
 }
 
-// Strip width and prefetch depth of each variant.  Variants whose LDS ring
-// would exceed 64 KiB for a given field count fall back to variant 0.
-constexpr int kVariants = 4;
-constexpr int kTY[kVariants] = {6, 6, 14, 14};
-constexpr int kD[kVariants] = {2, 4, 2, 4};
+// Strip width, prefetch depth and LDS cap of each variant.  Variants 0-3 keep
+// their LDS ring within 64 KiB; variant 4 (10-column strips, 12 wavefronts)
+// may use up to the 160 KiB of a compute unit, one workgroup per unit.  A
+// variant whose ring would exceed its cap for a given field count and working
+// type falls back to variant 0.
+constexpr int kVariants = 5;
+constexpr int kTY[kVariants] = {6, 6, 14, 14, 10};
+constexpr int kD[kVariants] = {2, 4, 2, 4, 2};
+constexpr int kLdsCap[kVariants] = {65536, 65536, 65536, 65536, 163840};
 
 template <typename T, typename C, int NF, int TY>
 constexpr int lds_bytes()
@@ -440,42 +444,48 @@ constexpr int lds_bytes()
     return (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
 }
 
-template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD>
+template <typename T, typename C, int NF, bool WS, bool WG, int V, int UPD>
 void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
-    if constexpr (lds_bytes<T, C, NF, TY>() <= 65536) {
+    constexpr int TY = kTY[V], D = kD[V];
+    if constexpr (lds_bytes<T, C, NF, TY>() <= kLdsCap[V]) {
         const Launch l = plan(g, TY);
         hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, UPD>), dim3(l.grid), dim3(64 * (TY + 2)), 0,
                            s, m, g, l.LX, l.nstrips, l.nblocks);
     } else {
-        go<T, C, NF, WS, WG, kTY[0], kD[0], UPD>(m, g, s);
+        go<T, C, NF, WS, WG, 0, UPD>(m, g, s);
     }
 }
 
-// Default variant per element type and field count, from sweeps on MI355X at
-// 4096 x 4096 x 64: 14-column strips (fewer halo waves per computed column)
-// wherever the LDS ring fits 64 KiB; the FP64 six-field kernels keep
-// 6-column strips.  Deeper prefetch (D = 4) measured no faster.
-// PW_MARCH_VARIANT=0..3 overrides the choice for sweeps.
-template <typename T, typename C, int NF>
+// Default variant per type pair, field count and output set, from sweeps on
+// MI355X at 4096 x 4096 x 64: 14-column strips (fewer halo waves per computed
+// column) wherever the registers allow 16 wavefronts; the six-field kernels
+// with FP64 arithmetic keep 6-column strips (their 150-190 registers allow 8
+// or 12 wavefronts per unit), except the FP32-storage adjoint, 11% faster in
+// 10-column strips.  Deeper prefetch (D = 4) measured no faster.
+// PW_MARCH_VARIANT=0..4 overrides the choice for sweeps.
+template <typename T, typename C, int NF, bool WS>
 int default_variant()
 {
-    return (NF == 3 || sizeof(C) == 4) ? 2 : 0;
+    if (NF == 3 || sizeof(C) == 4) return 2;
+    if (sizeof(T) == 4 && !WS) return 4;
+    return 0;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
-    int v = default_variant<T, C, NF>();
+    int v = default_variant<T, C, NF, WS>();
     if (const char* e = std::getenv("PW_MARCH_VARIANT")) {
         const int q = std::atoi(e);
         if (q >= 0 && q < kVariants) v = q;
     }
     switch (v) {
-    case 1: go<T, C, NF, WS, WG, kTY[1], kD[1], UPD>(m, g, s); break;
-    case 2: go<T, C, NF, WS, WG, kTY[2], kD[2], UPD>(m, g, s); break;
-    case 3: go<T, C, NF, WS, WG, kTY[3], kD[3], UPD>(m, g, s); break;
-    default: go<T, C, NF, WS, WG, kTY[0], kD[0], UPD>(m, g, s); break;
+    case 1: go<T, C, NF, WS, WG, 1, UPD>(m, g, s); break;
+    case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, s); break;
+    case 3: go<T, C, NF, WS, WG, 3, UPD>(m, g, s); break;
+    case 4: go<T, C, NF, WS, WG, 4, UPD>(m, g, s); break;
+    default: go<T, C, NF, WS, WG, 0, UPD>(m, g, s); break;
     }
 }
 

@@ -110,7 +110,7 @@ def test_fused_separate_and_kernels_agree(pw, kind):
     old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
     try:
         os.environ["PW_MARCH_LX"] = "7"
-        for v in ("0", "1", "2", "3"):
+        for v in ("0", "1", "2", "3", "4"):
             os.environ["PW_MARCH_VARIANT"] = v
             f = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *c, H))
             for a, b in zip(results["direct"], f):

@@ -117,7 +117,7 @@ def test_fused_equals_separate(pw, kernel):
         assert np.array_equal(interior(a), interior(b))
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
 def test_every_march_variant_matches_direct(pw, variant):
     fields, lams, coef = host_case(45, 31, 64, 49, lam_seed=50)
     st, sl = dev_f32(pw, as_f32(fields)), dev_f32(pw, as_f32(lams))

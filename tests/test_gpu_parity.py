@@ -199,7 +199,7 @@ def test_march_and_direct_agree_bitwise(pw, dtype):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_every_march_variant_matches_direct(pw, variant, dtype):
     """Each strip-width / prefetch-depth variant of the x-marching kernel (and
