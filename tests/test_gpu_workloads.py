@@ -284,3 +284,82 @@ def test_paper_scale_sampled(pw):
             assert np.all(np.abs(got - ref) <= 16 * 2.0 ** -24 * mm + 1e-30), i
     _report("paper_scale_sampled.json", rec)
     log(json.dumps(rec))
+
+
+# fused forward + adjoint at 4096x4096x64 for the other dtypes, in the launch
+# configuration bench.py times: device-generated inputs (the generator rounds
+# to the storage type, as inputs.round_storage does on the host), four sampled
+# x-planes against the FP64 oracle on the same rounded values
+DTYPE_CASES = {
+    # kind: (storage dtype, compute, fwd units of 2^-24 T, adj units, u16, subnormal, fwd bitwise-rounded)
+    "f32": (torch.float32, None, 16, 32, 0.0, 0.0, False),
+    "f32f64": (torch.float32, torch.float64, 0, 0, 0.0, 0.0, True),
+    "f16": (torch.float16, None, 16, 32, 2.0 ** -11, 2.0 ** -25, False),
+    "bf16": (torch.bfloat16, None, 16, 32, 2.0 ** -8, 0.0, False),
+}
+
+
+@pytest.mark.parametrize("kind", list(DTYPE_CASES))
+def test_paper_scale_sampled_dtypes(pw, kind):
+    dtype, compute, fu, gu_units, u16, sub, rounded_fwd = DTYPE_CASES[kind]
+    nx, ny, nz, seed = 4096, 4096, 64, 4
+    log("paper scale 4096x4096x64 fused %s (device-generated inputs)" % kind)
+    shape = (nx + 2 * H, ny + 2 * H, nz + 2 * H)
+    mk = lambda: torch.empty(shape, dtype=dtype, device=DEV)
+    coef = inputs.coefficients(nz)
+    f = [mk() for _ in range(3)]
+    l = [mk() for _ in range(3)]
+    for q, t in enumerate(f):
+        pw.fill_uniform(t, H, seed, q, 10.0, zero_lids=(q == 2))
+        pw.halo_periodic(t, H)
+    for q, t in enumerate(l):
+        pw.fill_uniform(t, H, seed, 3 + q, 1.0)
+        pw.halo_periodic(t, H)
+    out = pw.fwd_adj(*f, *l, *coef_dev(coef), H, out=[mk() for _ in range(6)], compute=compute)
+    torch.cuda.synchronize()
+    store = {torch.float32: "f32", torch.float16: "f16", torch.bfloat16: "bf16"}[dtype]
+    for i in (0, 2047, 4095, int(np.random.default_rng(5).integers(1, nx - 1))):
+        fs, ls = _host_slab(seed, nx, ny, nz, i, 1)
+        fs = [inputs.round_storage(a, store) for a in fs]
+        ls = [inputs.round_storage(a, store) for a in ls]
+        s_ref, s_mag = oracle.fwd(*fs, *coef, H), oracle.fwd(*fs, *coef, H, abs_bound=True)
+        g_ref, g_mag = oracle.adj(*fs, *ls, *coef, H), oracle.adj(*fs, *ls, *coef, H, abs_bound=True)
+        for q, (name, t) in enumerate(zip(("su", "sv", "sw", "gu", "gv", "gw"), out)):
+            got = t[i + H, H:-H, H:-H].cpu().double().numpy()
+            ref = (list(s_ref) + list(g_ref))[q][1 + H, H:-H, H:-H]
+            mag = (list(s_mag) + list(g_mag))[q][1 + H, H:-H, H:-H]
+            if rounded_fwd and q < 3:
+                assert np.array_equal(got, ref.astype(np.float32).astype(np.float64)), (i, name)
+                continue
+            if rounded_fwd:
+                bound = 2.0 ** -24 * np.abs(ref) + 32 * 2.0 ** -53 * mag + 1e-300
+            else:
+                units = fu if q < 3 else gu_units
+                bound = units * 2.0 ** -24 * mag + u16 * np.abs(ref) + sub + 1e-30
+            bad = np.abs(got - ref) > bound
+            assert not np.any(bad), (i, name, int(np.sum(bad)))
+    del out, f, l
+    torch.cuda.empty_cache()
+
+
+def test_paper_scale_sampled_update(pw):
+    """The fused Euler step u + dt*su at 4096x4096x64 FP64: sampled planes
+    equal the oracle's forward followed by the same two operations."""
+    nx, ny, nz, seed = 4096, 4096, 64, 4
+    log("paper scale 4096x4096x64 update f64")
+    shape = (nx + 2 * H, ny + 2 * H, nz + 2 * H)
+    coef = inputs.coefficients(nz)
+    f = [torch.empty(shape, dtype=torch.float64, device=DEV) for _ in range(3)]
+    for q, t in enumerate(f):
+        pw.fill_uniform(t, H, seed, q, 10.0, zero_lids=(q == 2))
+        pw.halo_periodic(t, H)
+    dt = 0.375
+    out = pw.fwd_update(*f, *coef_dev(coef), H, *f, dt)
+    torch.cuda.synchronize()
+    for i in (0, 1, 4095, 3001):
+        fs, _ = _host_slab(seed, nx, ny, nz, i, 1)
+        ref = oracle.fwd_update(*fs, *coef, H, *fs, dt)
+        for t, r in zip(out, ref):
+            assert np.array_equal(t[i + H, H:-H, H:-H].cpu().numpy(), r[1 + H, H:-H, H:-H]), i
+    del out, f
+    torch.cuda.empty_cache()
