@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kBlock) fwd_direct_kernel(FwdArgs<T> a, Geom g
         const Star<C> w = widen<C>(load_star<T, 2, false>(a.w, b, g.sx, g.sy, k, g.nz));
         const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, k, g.nz);
         C su, sv, sw;
-        pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
+        pw_fwd(u, v, w, cf, k, g.nz, su, sv, sw);
         if (UPD != 0) {
             const C beta = (C)a.beta;
             const C bu = UPD == 2 ? u.c : (C)a.b[0][b];
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kBlock) adj_direct_kernel(AdjArgs<T> a, Geom g
         const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, k, g.nz);
         if (FUSED) {
             C su, sv, sw;
-            pw_fwd_cell(u, v, w, cf, k, g.nz, su, sv, sw);
+            pw_fwd(u, v, w, cf, k, g.nz, su, sv, sw);
             a.su[b] = store_round<T>(su);
             a.sv[b] = store_round<T>(sv);
             a.sw[b] = store_round<T>(sw);

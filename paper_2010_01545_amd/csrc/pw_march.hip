@@ -368,7 +368,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                     const Star<W>& q = st[f];
                     sc[f] = Star<C>{(C)q.c, (C)q.xm, (C)q.xp, (C)q.ym, (C)q.yp, (C)q.zm, (C)q.zp, (C)q.d1, (C)q.d2};
                 }
-                if (WS) pw_fwd_cell(sc[0], sc[1], sc[2], cf, lane, NZ, out[0], out[1], out[2]);
+                if (WS) pw_fwd(sc[0], sc[1], sc[2], cf, lane, NZ, out[0], out[1], out[2]);
                 if (WG)
                     pw_adj_cell(sc[0], sc[1], sc[2], sc[NF - 3], sc[NF - 2], sc[NF - 1], cf, lane, NZ,
                                 out[3], out[4], out[5]);
