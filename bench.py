@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--no-paths", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-offload", action="store_true")
+    ap.add_argument("--no-medium", action="store_true",
+                    help="skip the cache-resident 256x256x64 record (its launches share the kernels' names)")
     ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64")
     args = ap.parse_args()
 
@@ -398,16 +400,18 @@ def main():
 
     # 256x256x64 (the medium workload): the forward's six FP64 arrays (221 MB)
     # fit the 256 MB Infinity Cache, so its rate is not an HBM figure
-    wm = inputs.WORKLOADS["medium"]
-    g = Grid(pw, torch, wm["nx"], wm["ny"], wm["nz"], h, torch.float64, wm["seed"], True)
-    cm = wm["nx"] * wm["ny"] * wm["nz"]
-    medium = {"workload": "medium %dx%dx%d FP64, 100 launches each" % (wm["nx"], wm["ny"], wm["nz"]),
-              "note": "fwd working set 221 MB fits the 256 MB Infinity Cache: not an HBM rate"}
-    for p in ("fwd", "fused"):
-        g.launch(pw, p)
-        medium[p] = path_record(p, 8, cm, time_launches(torch, lambda: g.launch(pw, p), 100))
-    del g
-    torch.cuda.empty_cache()
+    medium = None
+    if not args.no_medium:
+        wm = inputs.WORKLOADS["medium"]
+        g = Grid(pw, torch, wm["nx"], wm["ny"], wm["nz"], h, torch.float64, wm["seed"], True)
+        cm = wm["nx"] * wm["ny"] * wm["nz"]
+        medium = {"workload": "medium %dx%dx%d FP64, 100 launches each" % (wm["nx"], wm["ny"], wm["nz"]),
+                  "note": "fwd working set 221 MB fits the 256 MB Infinity Cache: not an HBM rate"}
+        for p in ("fwd", "fused"):
+            g.launch(pw, p)
+            medium[p] = path_record(p, 8, cm, time_launches(torch, lambda: g.launch(pw, p), 100))
+        del g
+        torch.cuda.empty_cache()
 
     kname = "fused_f64"
     traffic = measured_traffic(kname, args.workload)
