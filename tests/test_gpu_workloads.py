@@ -26,7 +26,7 @@ from _helpers import H, host_case, log, normwise, oracle_storage, rms_rel
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
-OUT = os.environ.get("PW_TEST_REPORT_DIR", "gpurun_out")
+OUT = os.environ.get("PW_TEST_REPORT_DIR", "test_reports")
 
 
 @pytest.fixture(scope="module")
