@@ -26,6 +26,7 @@ import hashlib
 import glob
 import json
 import os
+import re
 import sys
 import time
 
@@ -49,12 +50,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """Source text without comments and whitespace (a comment edit leaves the
+    kernels, and so their measured traffic, unchanged)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", "", text)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2010_01545_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+        with open(p, "r") as f:
             h.update(os.path.basename(p).encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

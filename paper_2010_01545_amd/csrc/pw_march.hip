@@ -198,9 +198,10 @@ struct MarchArgs {
     double tcx, tcy, beta;
 };
 
-// T: storage type (registers, LDS and DPP shifts work in it); C: arithmetic
-// type (T, or double for float storage).  TY: compute columns per workgroup
-// (TY + 2 wavefronts); D: planes prefetched beyond the current xp plane (D >= 2).
+// T: storage type; C: arithmetic type (T, or wider: double for float
+// storage, float for 16-bit storage); registers, LDS and DPP shifts work in
+// work_t<T, C>.  TY: compute columns per workgroup (TY + 2 wavefronts); D:
+// planes prefetched beyond the current xp plane (D >= 2).
 // UPD (forward only): 0 stores s; 1 stores b + beta * s with the base arrays
 // b streamed through the register ring like the fields (b may be the output
 // itself: each element is read planes before the same wave writes it); 2 the
