@@ -1,13 +1,15 @@
 """ctypes binding of libpwadvect (argument marshalling only).
 
-Each function takes torch tensors on a ROCm device, checks that they are
-contiguous and of one storage shape, and passes raw pointers, sizes and the
-current torch stream to the C entry point of the same name in
-``include/pwadvect.h``.  All computation happens in the HIP library; if it is
-not built, importing this module raises ImportError.
+Each function takes torch tensors (on a ROCm device; host tensors for
+``fwd_host``), checks that they are contiguous and of one storage shape, and
+passes raw pointers, sizes and the current torch stream to the C entry point
+of the same name in ``include/pwadvect.h``.  All computation happens in the
+HIP library; if it is not built, importing this module raises ImportError.
 
 Storage tensors have shape (nx+2h, ny+2h, nz+2h), z fastest; the grid size is
-taken from the shape and the ``halo`` argument.
+taken from the shape and the ``halo`` argument.  The storage dtype selects the
+element type (float64, float32, float16, bfloat16); ``compute=torch.float64``
+with float32 storage selects FP64 arithmetic (PW_F32_F64).
 """
 import ctypes
 import os
