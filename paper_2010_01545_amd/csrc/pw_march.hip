@@ -1,13 +1,14 @@
-// pw_march.hip -- x-marching PW advection kernels for 64-level columns.
+// pw_march.hip -- x-marching PW advection kernels for columns of up to 64 levels.
 //
 // Work decomposition.  A workgroup owns a strip of TY consecutive y-columns
 // (contiguous in memory, like the y-batches of the paper's section 3) and a
 // segment of LX consecutive x-planes, which it walks in increasing x (the
 // x-outer loop order of Listing 4).  It has TY + 2 wavefronts: wave w holds
-// y-column j0 - 1 + w, with lane k = level k of that column (nz == 64, so one
+// y-column j0 - 1 + w, with lane k = level k of that column (nz <= 64, so one
 // 64-wide wavefront covers a column and every global access of a wave is one
-// contiguous, coalesced run along z).  Waves 0 and TY + 1 only load the halo
-// columns; waves 1..TY load and compute.
+// contiguous, coalesced run along z; lanes k >= nz read zeros and store
+// nothing, as lanes past the end of a 64-level column do).  Waves 0 and
+// TY + 1 only load the halo columns; waves 1..TY load and compute.
 //
 // Reuse.  Each field (u, v, w and, for the adjoint, lu, lv, lw) is read from
 // HBM once per cell:
@@ -37,7 +38,7 @@
 
 namespace {
 
-constexpr int NZ = 64;   // levels per column = wavefront width
+constexpr int NZ = 64;   // wavefront width = most levels per column
 
 // Lane k receives lane k-1's value (wavefront shift right by one, DPP).
 __device__ __forceinline__ int dpp_from_below(int x)
@@ -250,17 +251,18 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
         const int pc = p < g.nx ? p : g.nx;       // planes past the end are never used
         return f + ((long long)(pc + g.h) * sx + (long long)(j + dj + g.h) * sy);
     };
-    const unsigned voff = (unsigned)(g.h + lane) * (unsigned)sizeof(T);  // interior level `lane`
+    // interior level `lane` (lanes past the column's nz levels: out of range)
+    const unsigned voff = lane < g.nz ? (unsigned)(g.h + lane) * (unsigned)sizeof(T) : kOutOfRange;
     // z-halo levels of an output column: lanes 0..h-1 bottom, h..2h-1 top
     const unsigned vpad = lane < g.h ? (unsigned)lane * (unsigned)sizeof(T)
-                        : (lane < 2 * g.h ? (unsigned)(NZ + lane) * (unsigned)sizeof(T) : kOutOfRange);
+                        : (lane < 2 * g.h ? (unsigned)(g.nz + lane) * (unsigned)sizeof(T) : kOutOfRange);
 
     // Multipliers are used with their level masks applied (see
     // pw_stencil.h): every operand of the gather is then a masked value, a
     // copy of one, or a DPP shift of one (shifts across the column ends read
     // 0).  The mask is applied where a freshly loaded plane is first used, so
     // that the prefetch is not waited for at the load.
-    const bool live_uv = lam_uv_live(lane, NZ), live_w = lam_w_live(lane, NZ);
+    const bool live_uv = lam_uv_live(lane, g.nz), live_w = lam_w_live(lane, g.nz);
     auto mask = [&](int f, W x) -> W {
         if (f < 3 || f >= NF) return x;
         return ((f == 5) ? live_w : live_uv) ? x : W(0);
@@ -296,7 +298,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
         else if (f % 3 == 1) carry[f] = mask(f, widen<T, W>(ld(f, i0, -1, stbytes))); // F(i0, j-1)
         else carry[f] = W(0);
     }
-    const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, lane, NZ);
+    // (lanes past the column read the top level's coefficients: tzc has nz entries)
+    const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, min(lane, g.nz - 1), g.nz);
 
     {
 #pragma unroll
@@ -369,9 +372,9 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                     const Star<W>& q = st[f];
                     sc[f] = Star<C>{(C)q.c, (C)q.xm, (C)q.xp, (C)q.ym, (C)q.yp, (C)q.zm, (C)q.zp, (C)q.d1, (C)q.d2};
                 }
-                if (WS) pw_fwd(sc[0], sc[1], sc[2], cf, lane, NZ, out[0], out[1], out[2]);
+                if (WS) pw_fwd(sc[0], sc[1], sc[2], cf, lane, g.nz, out[0], out[1], out[2]);
                 if (WG)
-                    pw_adj_cell(sc[0], sc[1], sc[2], sc[NF - 3], sc[NF - 2], sc[NF - 1], cf, lane, NZ,
+                    pw_adj_cell(sc[0], sc[1], sc[2], sc[NF - 3], sc[NF - 2], sc[NF - 1], cf, lane, g.nz,
                                 out[3], out[4], out[5]);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -495,7 +498,7 @@ void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 template <typename T>
 bool march_supported(const Geom& g)
 {
-    return g.nz == NZ && g.h <= 32;
+    return g.nz >= 2 && g.nz <= NZ && g.h <= 32;
 }
 
 template <typename T, typename C>

@@ -66,7 +66,7 @@ def run_fwd(pw, fields, coef, dtype, kernel, sentinel=True):
 
 
 def march_runs(pw, nz, kernel):
-    return kernel != "march" or nz == 64
+    return kernel != "march" or nz <= 64
 
 
 @pytest.mark.parametrize("kernel", ["direct", "march"])
@@ -74,7 +74,7 @@ def march_runs(pw, nz, kernel):
 def test_fwd_f64_matches_oracle(pw, shape, kernel):
     nx, ny, nz, seed = shape
     if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel is specialised for nz == 64")
+        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("fwd f64 %s %s" % (kernel, shape))
     fields, _, coef = host_case(nx, ny, nz, seed)
     ref = oracle.fwd(*oracle_storage(fields), *coef, H)
@@ -96,7 +96,7 @@ def test_fwd_f64_matches_oracle(pw, shape, kernel):
 def test_fwd_f32_error_bound(pw, shape, kernel):
     nx, ny, nz, seed = shape
     if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel is specialised for nz == 64")
+        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("fwd f32 %s %s" % (kernel, shape))
     fields, _, coef = host_case(nx, ny, nz, seed)
     f32 = [f.astype(np.float32).astype(np.float64) for f in fields]
@@ -133,7 +133,7 @@ def run_adj(pw, fields, lams, coef, dtype, kernel, fused=False):
 def test_adj_f64_matches_oracle(pw, shape, kernel):
     nx, ny, nz, seed = shape
     if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel is specialised for nz == 64")
+        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("adj f64 %s %s" % (kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
     ref = oracle.adj(*oracle_storage(fields), *oracle_storage(lams), *coef, H)
@@ -151,7 +151,7 @@ def test_adj_f32_error_bound(pw, shape, kernel):
     bound the FP32 arithmetic."""
     nx, ny, nz, seed = shape
     if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel is specialised for nz == 64")
+        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("adj f32 %s %s" % (kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 70)
     f32 = [a.astype(np.float32).astype(np.float64) for a in fields]
@@ -235,7 +235,7 @@ def test_other_halo_widths(pw, kernel, halo, shape):
     layer; the rest is layout): forward bitwise, adjoint within 1e-12."""
     nx, ny, nz, seed = shape
     if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel is specialised for nz == 64")
+        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("halo %d %s %s" % (halo, kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 5)
     tzc1, tzc2, tcx, tcy = coef
@@ -257,3 +257,23 @@ def test_other_halo_widths(pw, kernel, halo, shape):
         assert np.array_equal(inner_h(got.cpu().numpy()), inner_h(ref))
     for got, ref in zip(out[3:], ref_g):
         assert normwise(inner_h(got.cpu().numpy()), inner_h(ref)) <= 1e-12
+
+
+def test_march_selection_limits(pw):
+    """The x-marching kernel takes columns of 2..64 levels; asked for a taller
+    column it is refused before any launch, and "auto" falls back to the
+    direct kernel."""
+    fields, _, coef = host_case(4, 3, 65, 90)
+    st = pad_dev(pw, fields, torch.float64)
+    t1, t2 = torch.from_numpy(coef[0]).to(DEV), torch.from_numpy(coef[1]).to(DEV)
+    prev = pw.set_kernel("march")
+    try:
+        with pytest.raises(pw.PWError) as e:
+            pw.fwd(*st, t1, t2, coef[2], coef[3], H)
+        assert e.value.code == -5
+    finally:
+        pw.set_kernel(prev)
+    got = run_fwd(pw, fields, coef, torch.float64, "auto")
+    ref = oracle.fwd(*oracle_storage(fields), *coef, H)
+    for g, r in zip(got, ref):
+        assert np.array_equal(oracle.interior(g, H), oracle.interior(r, H))
