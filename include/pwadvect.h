@@ -98,7 +98,7 @@ enum {
 enum {
     PW_KERNEL_AUTO = 0,   /* x-marching kernel where it applies, else direct */
     PW_KERNEL_DIRECT = 1, /* one thread per storage level, any nz >= 2 */
-    PW_KERNEL_MARCH = 2   /* x-marching, LDS-staged kernel; nz <= 64, halo <= 32 */
+    PW_KERNEL_MARCH = 2   /* x-marching, LDS-staged kernel; halo <= 32 */
 };
 
 /*

@@ -243,7 +243,7 @@ int do_fwd(const void* u, const void* v, const void* w, const double* tzc1, cons
             for (int q = 0; q < 3; q++) fields[nf++] = ba[q];
     }
     const int kern = resolve_kernel<T>(g, fields, nf);
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz <= 64, halo <= 32 and 16-byte aligned arrays");
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and 16-byte aligned arrays");
     FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw, upd,
                  {nullptr, nullptr, nullptr}, beta};
     if (base)
@@ -289,7 +289,7 @@ int do_adj(const void* u, const void* v, const void* w, const void* lu, const vo
     for (int q = 0; q < 6; q++) fields[nf++] = in[q];
     for (int q = 0; q < nout; q++) fields[nf++] = out[q];
     const int kern = resolve_kernel<T>(g, fields, nf);
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz <= 64, halo <= 32 and 16-byte aligned arrays");
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and 16-byte aligned arrays");
     AdjArgs<T> a{(const T*)u, (const T*)v, (const T*)w, (const T*)lu, (const T*)lv, (const T*)lw,
                  tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw, (T*)gu, (T*)gv, (T*)gw};
     (void)hipGetLastError();
@@ -418,7 +418,7 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
     sg.nx = chunk;
     const Arr ws[1] = {{workspace, need, 16, "workspace"}};
     const int kern = with_types(dtype, [&](auto t, auto) { return resolve_kernel<decltype(t)>(sg, ws, 1); });
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs nz <= 64 and halo <= 32");
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32");
     // mapped pinned outputs are written by a copy kernel unless
     // PW_OFFLOAD_COPY_OUT=runtime asks for the runtime's copies
     void* od[3] = {nullptr, nullptr, nullptr};

@@ -42,7 +42,7 @@ struct AdjArgs {
 template <typename T, typename C> void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
 template <typename T, typename C> void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
 
-// x-marching kernels (2 <= nz <= 64, halo <= 32, 16-byte aligned arrays).
+// x-marching kernels (any nz >= 2, halo <= 32, 16-byte aligned arrays).
 template <typename T> bool march_supported(const Geom& g);
 template <typename T, typename C> void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
 template <typename T, typename C> void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s);

@@ -1,4 +1,4 @@
-// pw_march.hip -- x-marching PW advection kernels for columns of up to 64 levels.
+// pw_march.hip -- x-marching PW advection kernels (columns of any height).
 //
 // Work decomposition.  A workgroup owns a strip of TY consecutive y-columns
 // (contiguous in memory, like the y-batches of the paper's section 3) and a
@@ -9,6 +9,10 @@
 // contiguous, coalesced run along z; lanes k >= nz read zeros and store
 // nothing, as lanes past the end of a 64-level column do).  Waves 0 and
 // TY + 1 only load the halo columns; waves 1..TY load and compute.
+// Taller columns are cut into z-chunks of 62 levels, one chunk per
+// workgroup: lane l holds level 62 c - 1 + l, lanes 0 and 63 are the chunk's
+// halo levels (loaded, never stored), so the z-neighbours of lanes 1..62
+// still come from wavefront shifts.
 //
 // Reuse.  Each field (u, v, w and, for the adjoint, lu, lv, lw) is read from
 // HBM once per cell:
@@ -39,6 +43,7 @@
 namespace {
 
 constexpr int NZ = 64;   // wavefront width = most levels per column
+constexpr int kChunk = NZ - 2;   // levels a z-chunk of a taller column owns
 
 // Lane k receives lane k-1's value (wavefront shift right by one, DPP).
 __device__ __forceinline__ int dpp_from_below(int x)
@@ -209,7 +214,7 @@ struct MarchArgs {
 // same with b = (u, v, w), whose centre values are already in the ring.
 template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD = 0>
 __global__ void __launch_bounds__(64 * (TY + 2))
-march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
+march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks)
 {
     static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
     static_assert(UPD == 0 || (NF == 3 && WS && !WG), "the update form is a forward-only epilogue");
@@ -233,7 +238,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
     const int L = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (L >= nblocks) return;
     const int strip = L % nstrips;
-    const int seg = L / nstrips;
+    const int chunk = (L / nstrips) % nchunk;
+    const int seg = L / nstrips / nchunk;
     const int j0 = strip * TY;
     const int ncols = min(TY, g.ny - j0);
     const int i0 = seg * LX;
@@ -251,18 +257,24 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
         const int pc = p < g.nx ? p : g.nx;       // planes past the end are never used
         return f + ((long long)(pc + g.h) * sx + (long long)(j + dj + g.h) * sy);
     };
-    // interior level `lane` (lanes past the column's nz levels: out of range)
-    const unsigned voff = lane < g.nz ? (unsigned)(g.h + lane) * (unsigned)sizeof(T) : kOutOfRange;
-    // z-halo levels of an output column: lanes 0..h-1 bottom, h..2h-1 top
-    const unsigned vpad = lane < g.h ? (unsigned)lane * (unsigned)sizeof(T)
-                        : (lane < 2 * g.h ? (unsigned)(g.nz + lane) * (unsigned)sizeof(T) : kOutOfRange);
+    // level of this lane; loads at levels outside 0..nz-1 are out of range
+    // (read zero), stores only from the lanes the chunk owns
+    const int k = nchunk == 1 ? lane : chunk * kChunk - 1 + lane;
+    const bool own = nchunk == 1 || (lane >= 1 && lane <= kChunk);
+    const unsigned voff = (k >= 0 && k < g.nz) ? (unsigned)(g.h + k) * (unsigned)sizeof(T) : kOutOfRange;
+    const unsigned vst = own ? voff : kOutOfRange;
+    // z-halo levels of an output column: lanes 0..h-1 bottom (first chunk),
+    // h..2h-1 top (last chunk)
+    const unsigned vpad = (lane < g.h && chunk == 0) ? (unsigned)lane * (unsigned)sizeof(T)
+                        : (lane >= g.h && lane < 2 * g.h && chunk == nchunk - 1)
+                              ? (unsigned)(g.nz + lane) * (unsigned)sizeof(T) : kOutOfRange;
 
     // Multipliers are used with their level masks applied (see
     // pw_stencil.h): every operand of the gather is then a masked value, a
     // copy of one, or a DPP shift of one (shifts across the column ends read
     // 0).  The mask is applied where a freshly loaded plane is first used, so
     // that the prefetch is not waited for at the load.
-    const bool live_uv = lam_uv_live(lane, g.nz), live_w = lam_w_live(lane, g.nz);
+    const bool live_uv = lam_uv_live(k, g.nz), live_w = lam_w_live(k, g.nz);
     auto mask = [&](int f, W x) -> W {
         if (f < 3 || f >= NF) return x;
         return ((f == 5) ? live_w : live_uv) ? x : W(0);
@@ -298,8 +310,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
         else if (f % 3 == 1) carry[f] = mask(f, widen<T, W>(ld(f, i0, -1, stbytes))); // F(i0, j-1)
         else carry[f] = W(0);
     }
-    // (lanes past the column read the top level's coefficients: tzc has nz entries)
-    const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, min(lane, g.nz - 1), g.nz);
+    // (lanes outside the column read the nearest level's coefficients: tzc has nz entries)
+    const LevelCoef<C> cf = level_coef<C>(a.tzc1, a.tzc2, (C)a.tcx, (C)a.tcy, min(max(k, 0), g.nz - 1), g.nz);
 
     {
 #pragma unroll
@@ -372,9 +384,9 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                     const Star<W>& q = st[f];
                     sc[f] = Star<C>{(C)q.c, (C)q.xm, (C)q.xp, (C)q.ym, (C)q.yp, (C)q.zm, (C)q.zp, (C)q.d1, (C)q.d2};
                 }
-                if (WS) pw_fwd(sc[0], sc[1], sc[2], cf, lane, g.nz, out[0], out[1], out[2]);
+                if (WS) pw_fwd(sc[0], sc[1], sc[2], cf, k, g.nz, out[0], out[1], out[2]);
                 if (WG)
-                    pw_adj_cell(sc[0], sc[1], sc[2], sc[NF - 3], sc[NF - 2], sc[NF - 1], cf, lane, g.nz,
+                    pw_adj_cell(sc[0], sc[1], sc[2], sc[NF - 3], sc[NF - 2], sc[NF - 1], cf, k, g.nz,
                                 out[3], out[4], out[5]);
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -392,7 +404,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
                 C o = out[q];
                 if (UPD == 1 && q < 3) o = pw_update((C)widen<T, W>(R[NF + q][rc]), (C)a.beta, o);
                 if (UPD == 2 && q < 3) o = pw_update((C)R[q][rc], (C)a.beta, o);
-                buf_store(store_round<T>(o), r, voff);
+                buf_store(store_round<T>(o), r, vst);
                 buf_store(T(0), r, vpad);
             }
 
@@ -410,24 +422,25 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nblocks)
 }
 
 struct Launch {
-    int LX, nstrips, nblocks, grid;
+    int LX, nstrips, nchunk, nblocks, grid;
 };
 
 Launch plan(const Geom& g, int TY)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
+    l.nchunk = g.nz <= NZ ? 1 : (g.nz + kChunk - 1) / kChunk;
     int lx = 0;
     if (const char* e = std::getenv("PW_MARCH_LX")) lx = std::atoi(e);
     if (lx <= 0) {
         // Segments of up to 128 planes (measured best at 4096 x 4096 x 64);
         // shorter ones on small grids so that about 8192 workgroups exist.
-        const long long want = ((long long)g.nx * l.nstrips + 8191) / 8192;
+        const long long want = ((long long)g.nx * l.nstrips * l.nchunk + 8191) / 8192;
         lx = want < 16 ? 16 : (want > 128 ? 128 : (int)want);
     }
     l.LX = lx;
     const int nseg = (g.nx + lx - 1) / lx;
-    l.nblocks = l.nstrips * nseg;
+    l.nblocks = l.nstrips * l.nchunk * nseg;
     l.grid = ((l.nblocks + 7) / 8) * 8;
     return l;
 }
@@ -455,7 +468,7 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
     if constexpr (lds_bytes<T, C, NF, TY>() <= kLdsCap[V]) {
         const Launch l = plan(g, TY);
         hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, UPD>), dim3(l.grid), dim3(64 * (TY + 2)), 0,
-                           s, m, g, l.LX, l.nstrips, l.nblocks);
+                           s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
     } else {
         go<T, C, NF, WS, WG, 0, UPD>(m, g, s);
     }
@@ -498,7 +511,7 @@ void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 template <typename T>
 bool march_supported(const Geom& g)
 {
-    return g.nz >= 2 && g.nz <= NZ && g.h <= 32;
+    return g.nz >= 2 && g.h <= 32;
 }
 
 template <typename T, typename C>

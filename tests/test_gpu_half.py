@@ -66,8 +66,6 @@ def with_kernel(pw, kernel, fn):
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
 def test_fwd_and_adj_bounds(pw, shape, kind, kernel):
     nx, ny, nz, seed = shape
-    if kernel == "march" and nz > 64:
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     dtype, u16, sub = TYPES[kind]
     log("%s fwd/adj %s %s" % (kind, kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 1)

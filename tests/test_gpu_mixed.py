@@ -65,8 +65,6 @@ def interior(a):
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
 def test_fwd_is_rounded_oracle(pw, shape, kernel):
     nx, ny, nz, seed = shape
-    if kernel == "march" and nz > 64:
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("mixed fwd %s %s" % (kernel, shape))
     fields, _, coef = host_case(nx, ny, nz, seed)
     f32 = as_f32(fields)
@@ -87,8 +85,6 @@ def test_fwd_is_rounded_oracle(pw, shape, kernel):
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
 def test_adj_within_one_rounding(pw, shape, kernel):
     nx, ny, nz, seed = shape
-    if kernel == "march" and nz > 64:
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("mixed adj %s %s" % (kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 9)
     f32, l32 = as_f32(fields), as_f32(lams)

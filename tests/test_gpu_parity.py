@@ -26,7 +26,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
 SHAPES = [(32, 32, 64, 0), (5, 7, 3, 1), (33, 17, 65, 2), (3, 3, 3, 3), (1, 1, 64, 4), (2, 3, 2, 5),
-          (1, 9, 64, 6), (17, 1, 64, 7), (40, 24, 64, 8), (7, 130, 64, 9)]
+          (1, 9, 64, 6), (17, 1, 64, 7), (40, 24, 64, 8), (7, 130, 64, 9), (9, 7, 124, 10), (6, 5, 200, 11)]
 
 
 @pytest.fixture(scope="module")
@@ -65,16 +65,10 @@ def run_fwd(pw, fields, coef, dtype, kernel, sentinel=True):
     return [o.cpu().double().numpy() for o in outs]
 
 
-def march_runs(pw, nz, kernel):
-    return kernel != "march" or nz <= 64
-
-
 @pytest.mark.parametrize("kernel", ["direct", "march"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
 def test_fwd_f64_matches_oracle(pw, shape, kernel):
     nx, ny, nz, seed = shape
-    if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("fwd f64 %s %s" % (kernel, shape))
     fields, _, coef = host_case(nx, ny, nz, seed)
     ref = oracle.fwd(*oracle_storage(fields), *coef, H)
@@ -95,8 +89,6 @@ def test_fwd_f64_matches_oracle(pw, shape, kernel):
 @pytest.mark.parametrize("shape", SHAPES[:6], ids=lambda s: "x".join(map(str, s[:3])))
 def test_fwd_f32_error_bound(pw, shape, kernel):
     nx, ny, nz, seed = shape
-    if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("fwd f32 %s %s" % (kernel, shape))
     fields, _, coef = host_case(nx, ny, nz, seed)
     f32 = [f.astype(np.float32).astype(np.float64) for f in fields]
@@ -132,8 +124,6 @@ def run_adj(pw, fields, lams, coef, dtype, kernel, fused=False):
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
 def test_adj_f64_matches_oracle(pw, shape, kernel):
     nx, ny, nz, seed = shape
-    if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("adj f64 %s %s" % (kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
     ref = oracle.adj(*oracle_storage(fields), *oracle_storage(lams), *coef, H)
@@ -150,8 +140,6 @@ def test_adj_f32_error_bound(pw, shape, kernel):
     factors, so 32 units of 2^-24 times the sum of their absolute values
     bound the FP32 arithmetic."""
     nx, ny, nz, seed = shape
-    if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("adj f32 %s %s" % (kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 70)
     f32 = [a.astype(np.float32).astype(np.float64) for a in fields]
@@ -234,8 +222,6 @@ def test_other_halo_widths(pw, kernel, halo, shape):
     """Storage with halo 1, 3 and 5 (the scheme reads only the first halo
     layer; the rest is layout): forward bitwise, adjoint within 1e-12."""
     nx, ny, nz, seed = shape
-    if not march_runs(pw, nz, kernel):
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("halo %d %s %s" % (halo, kernel, shape))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 5)
     tzc1, tzc2, tcx, tcy = coef
@@ -260,20 +246,53 @@ def test_other_halo_widths(pw, kernel, halo, shape):
 
 
 def test_march_selection_limits(pw):
-    """The x-marching kernel takes columns of 2..64 levels; asked for a taller
-    column it is refused before any launch, and "auto" falls back to the
+    """The x-marching kernel takes halos of at most 32 levels; asked for a
+    wider one it is refused before any launch, and "auto" falls back to the
     direct kernel."""
-    fields, _, coef = host_case(4, 3, 65, 90)
-    st = pad_dev(pw, fields, torch.float64)
+    halo = 33
+    fields, _, coef = host_case(4, 3, 8, 90)
+    st = [pw.pad_periodic(t, halo) for t in to_dev(fields, torch.float64)]
     t1, t2 = torch.from_numpy(coef[0]).to(DEV), torch.from_numpy(coef[1]).to(DEV)
     prev = pw.set_kernel("march")
     try:
         with pytest.raises(pw.PWError) as e:
-            pw.fwd(*st, t1, t2, coef[2], coef[3], H)
+            pw.fwd(*st, t1, t2, coef[2], coef[3], halo)
         assert e.value.code == -5
     finally:
         pw.set_kernel(prev)
-    got = run_fwd(pw, fields, coef, torch.float64, "auto")
-    ref = oracle.fwd(*oracle_storage(fields), *coef, H)
+    got = pw.fwd(*st, t1, t2, coef[2], coef[3], halo)
+    torch.cuda.synchronize()
+    ref = oracle.fwd(*[oracle.pad_periodic(a, halo) for a in fields], *coef, halo)
     for g, r in zip(got, ref):
-        assert np.array_equal(oracle.interior(g, H), oracle.interior(r, H))
+        gi = g.cpu().numpy()[halo:-halo, halo:-halo, halo:-halo]
+        assert np.array_equal(gi, r[halo:-halo, halo:-halo, halo:-halo])
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_tall_columns_every_variant_matches_direct(pw, variant, dtype):
+    """Columns taller than a wavefront are marched in z-chunks of 62 levels
+    (chunk halo lanes 0 and 63): every variant, with short x-segments, gives
+    the direct kernel's bits for the forward, the adjoint and the fused pass."""
+    fields, lams, coef = host_case(13, 11, 150, 15, lam_seed=65)
+    ref_f = run_fwd(pw, fields, coef, dtype, "direct", sentinel=False)
+    ref_a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
+    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
+    os.environ["PW_MARCH_VARIANT"] = variant
+    os.environ["PW_MARCH_LX"] = "4"
+    try:
+        got_f = run_fwd(pw, fields, coef, dtype, "march", sentinel=True)
+        got_a = run_adj(pw, fields, lams, coef, dtype, "march", fused=True)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    for x, y in zip(ref_f + ref_a, got_f + got_a):
+        assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
+    for g in got_f:   # every interior column fully written, halo columns untouched
+        col = g[H:-H, H:-H, :]
+        assert not np.any(np.isnan(col))
+        assert np.all(col[:, :, :H] == 0) and np.all(col[:, :, -H:] == 0)
+        assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[:, :H]))

@@ -73,8 +73,6 @@ def check_layout(o):
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:3])))
 def test_update_f64_bitwise(pw, shape, kernel, mode):
     nx, ny, nz, seed = shape
-    if kernel == "march" and nz > 64:
-        pytest.skip("x-marching kernel runs columns of at most 64 levels")
     log("update f64 %s %s %s" % (kernel, mode, shape))
     fields, base, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 3)
     beta = 0.37 if mode != "in_place" else 1.0
