@@ -3,12 +3,20 @@
 // Work decomposition.  A workgroup owns a strip of TY consecutive y-columns
 // (contiguous in memory, like the y-batches of the paper's section 3) and a
 // segment of LX consecutive x-planes, which it walks in increasing x (the
-// x-outer loop order of Listing 4).  It has TY + 2 wavefronts: wave w holds
-// y-column j0 - 1 + w, with lane k = level k of that column (nz <= 64, so one
-// 64-wide wavefront covers a column and every global access of a wave is one
-// contiguous, coalesced run along z; lanes k >= nz read zeros and store
-// nothing, as lanes past the end of a 64-level column do).  Waves 0 and
-// TY + 1 only load the halo columns; waves 1..TY load and compute.
+// x-outer loop order of Listing 4).  Slot c of the strip is y-column
+// j0 - 1 + c: slots 1..TY are the strip's columns, slots 0 and TY + 1 its
+// y-halo columns.  A wavefront holds one slot, with lane k = level k of that
+// column (nz <= 64, so one 64-wide wavefront covers a column and every global
+// access of a wave is one contiguous, coalesced run along z; lanes k >= nz
+// read zeros and store nothing, as lanes past the end of a 64-level column
+// do).  Two ways to carry the halo columns:
+//   * halo waves: TY + 2 wavefronts, wave w = slot w; waves 0 and TY + 1
+//     only load;
+//   * edge waves: TY wavefronts, wave w = slot w + 1, all computing; the
+//     first and last wave also load a halo column, through a second register
+//     ring.  With TY a multiple of 4 the arithmetic spreads evenly over the
+//     four SIMDs of a compute unit, which pays where the arithmetic, not HBM,
+//     sets the pace.
 // Taller columns are cut into z-chunks of 62 levels, one chunk per
 // workgroup: lane l holds level 62 c - 1 + l, lanes 0 and 63 are the chunk's
 // halo levels (loaded, never stored), so the z-neighbours of lanes 1..62
@@ -206,19 +214,21 @@ struct MarchArgs {
 
 // T: storage type; C: arithmetic type (T, or wider: double for float
 // storage, float for 16-bit storage); registers, LDS and DPP shifts work in
-// work_t<T, C>.  TY: compute columns per workgroup (TY + 2 wavefronts); D:
-// planes prefetched beyond the current xp plane (D >= 2).
+// work_t<T, C>.  TY: compute columns per workgroup; D: planes prefetched
+// beyond the current xp plane (D >= 2); EH: halo columns carried by the edge
+// waves (TY wavefronts) instead of two halo waves (TY + 2 wavefronts).
 // UPD (forward only): 0 stores s; 1 stores b + beta * s with the base arrays
 // b streamed through the register ring like the fields (b may be the output
 // itself: each element is read planes before the same wave writes it); 2 the
 // same with b = (u, v, w), whose centre values are already in the ring.
-template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, int UPD = 0>
-__global__ void __launch_bounds__(64 * (TY + 2))
+template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, bool EH, int UPD = 0>
+__global__ void __launch_bounds__(64 * (EH ? TY : TY + 2))
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks)
 {
     static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
+    static_assert(!EH || TY >= 2, "the two halo columns belong to different edge waves");
     static_assert(UPD == 0 || (NF == 3 && WS && !WG), "the update form is a forward-only epilogue");
-    constexpr int NCOL = TY + 2;
+    constexpr int NCOL = TY + 2;    // LDS slots
     constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
     constexpr int U = D + 3;        // register ring length
     constexpr int NR = NF + (UPD == 1 ? 3 : 0);   // ring rows: fields, then base arrays
@@ -244,9 +254,16 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
     const int ncols = min(TY, g.ny - j0);
     const int i0 = seg * LX;
     const int i1 = min(i0 + LX, g.nx);
-    const int j = j0 - 1 + wave;
-    const bool loads = wave <= ncols + 1;        // column j in [j0-1, j0+ncols]
-    const bool comp = wave >= 1 && wave <= ncols; // column j in [j0, j0+ncols)
+    const int slot = EH ? wave + 1 : wave;
+    const int j = j0 - 1 + slot;
+    const bool loads = slot <= ncols + 1;         // column j in [j0-1, j0+ncols]
+    const bool comp = slot >= 1 && slot <= ncols; // column j in [j0, j0+ncols)
+    // Edge waves: the first wave also carries column j0 - 1, the last wave of
+    // a full strip column j0 + TY (in a narrower strip the wave of slot
+    // ncols + 1 loads that column as its own).
+    const bool halo = EH && (wave == 0 || (wave == TY - 1 && ncols == TY));
+    const int hdj = wave == 0 ? -1 : 1;           // halo column relative to j
+    const int hslot = wave == 0 ? 0 : TY + 1;
     const long long sx = g.sx;
     const int sy = g.sy;
     const int colbytes = g.Sz * (int)sizeof(T);
@@ -290,6 +307,9 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
         const bool used = f < NF ? pl <= i1 : (pl >= i0 && pl < i1);
         return used ? ldbytes : 0;
     };
+    // the halo ring of an edge wave holds planes i0 .. i1 of the fields, raw
+    // until deposited
+    auto halo_bytes = [&](int pl) -> int { return pl <= i1 ? colbytes : 0; };
 
     // Ring planes become values (widened, masked) where they are first used:
     // u/w-type plane q in step q-1 (as x+1 and LDS deposit), v-type plane q in
@@ -303,6 +323,13 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
             const W x = ld(f, i0 - 1 + t, 0, ring_bytes(f, i0 - 1 + t));
             R[f][t] = (f < NF && t < (f % 3 == 1 ? 3 : 2)) ? mask(f, widen<T, W>(x)) : x;
         }
+    W H[NF][U];
+    if (halo) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int t = 1; t < D + 2; ++t) H[f][t] = ld(f, i0 - 1 + t, hdj, halo_bytes(i0 - 1 + t));
+    }
     W carry[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -317,11 +344,24 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int t = f / 3;
-            if (f % 3 == 0) s_uw[2 * t][i0 & 1][wave][lane] = R[f][1];
-            if (f % 3 == 2) s_uw[2 * t + 1][i0 & 1][wave][lane] = R[f][1];
+            if (f % 3 == 0) s_uw[2 * t][i0 & 1][slot][lane] = R[f][1];
+            if (f % 3 == 2) s_uw[2 * t + 1][i0 & 1][slot][lane] = R[f][1];
             if (f % 3 == 1) {
-                s_v[t][i0 % 3][wave][lane] = R[f][1];
-                s_v[t][(i0 + 1) % 3][wave][lane] = R[f][2];
+                s_v[t][i0 % 3][slot][lane] = R[f][1];
+                s_v[t][(i0 + 1) % 3][slot][lane] = R[f][2];
+            }
+        }
+        if (halo) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const int t = f / 3;
+                const W h1 = mask(f, widen<T, W>(H[f][1]));
+                if (f % 3 == 0) s_uw[2 * t][i0 & 1][hslot][lane] = h1;
+                if (f % 3 == 2) s_uw[2 * t + 1][i0 & 1][hslot][lane] = h1;
+                if (f % 3 == 1) {
+                    s_v[t][i0 % 3][hslot][lane] = h1;
+                    s_v[t][(i0 + 1) % 3][hslot][lane] = mask(f, widen<T, W>(H[f][2]));
+                }
             }
         }
     }
@@ -341,6 +381,10 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
             // prefetch plane p + D + 1
 #pragma unroll
             for (int f = 0; f < NR; ++f) R[f][rnew] = ld(f, p + D + 1, 0, ring_bytes(f, p + D + 1));
+            if (halo) {  // only the edge waves spend memory instructions on the halo
+#pragma unroll
+                for (int f = 0; f < NF; ++f) H[f][rnew] = ld(f, p + D + 1, hdj, halo_bytes(p + D + 1));
+            }
 
             // first use of plane p+1 (u/w-type) and p+2 (v-type deposit)
 #pragma unroll
@@ -362,18 +406,18 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
                     q.zm = below(q.c);
                     q.zp = above(q.c);
                     if (f % 3 == 0) {            // u-type
-                        q.ym = s_uw[2 * t][pu][wave - 1][lane];
-                        q.yp = s_uw[2 * t][pu][wave + 1][lane];
+                        q.ym = s_uw[2 * t][pu][slot - 1][lane];
+                        q.yp = s_uw[2 * t][pu][slot + 1][lane];
                         q.d1 = carry[f];         // F(p-1, j+1)
                         q.d2 = above(q.xm);      // F(p-1, j, k+1)
                     } else if (f % 3 == 1) {     // v-type
                         q.ym = carry[f];         // F(p, j-1)
-                        q.yp = s_v[t][v0][wave + 1][lane];
-                        q.d1 = s_v[t][v1][wave - 1][lane];  // F(p+1, j-1)
+                        q.yp = s_v[t][v0][slot + 1][lane];
+                        q.d1 = s_v[t][v1][slot - 1][lane];  // F(p+1, j-1)
                         q.d2 = above(q.ym);      // F(p, j-1, k+1)
                     } else {                     // w-type
-                        q.ym = s_uw[2 * t + 1][pu][wave - 1][lane];
-                        q.yp = s_uw[2 * t + 1][pu][wave + 1][lane];
+                        q.ym = s_uw[2 * t + 1][pu][slot - 1][lane];
+                        q.yp = s_uw[2 * t + 1][pu][slot + 1][lane];
                         q.d1 = below(q.xp);      // F(p+1, j, k-1)
                         q.d2 = below(q.yp);      // F(p, j+1, k-1)
                     }
@@ -412,9 +456,18 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const int t = f / 3;
-                if (f % 3 == 0) s_uw[2 * t][pu ^ 1][wave][lane] = R[f][rq0];
-                if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][wave][lane] = R[f][rq0];
-                if (f % 3 == 1) s_v[t][v2][wave][lane] = R[f][rq1];
+                if (f % 3 == 0) s_uw[2 * t][pu ^ 1][slot][lane] = R[f][rq0];
+                if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][slot][lane] = R[f][rq0];
+                if (f % 3 == 1) s_v[t][v2][slot][lane] = R[f][rq1];
+            }
+            if (halo) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int t = f / 3;
+                    if (f % 3 == 0) s_uw[2 * t][pu ^ 1][hslot][lane] = mask(f, widen<T, W>(H[f][rq0]));
+                    if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][hslot][lane] = mask(f, widen<T, W>(H[f][rq0]));
+                    if (f % 3 == 1) s_v[t][v2][hslot][lane] = mask(f, widen<T, W>(H[f][rq1]));
+                }
             }
             __syncthreads();
         }
@@ -445,15 +498,15 @@ Launch plan(const Geom& g, int TY)
     return l;
 }
 
-// Strip width, prefetch depth and LDS cap of each variant.  Variants 0-3 keep
-// their LDS ring within 64 KiB; variant 4 (10-column strips, 12 wavefronts)
-// may use up to the 160 KiB of a compute unit, one workgroup per unit.  A
-// variant whose ring would exceed its cap for a given field count and working
-// type falls back to variant 0.
-constexpr int kVariants = 5;
-constexpr int kTY[kVariants] = {6, 6, 14, 14, 10};
-constexpr int kD[kVariants] = {2, 4, 2, 4, 2};
-constexpr int kLdsCap[kVariants] = {65536, 65536, 65536, 65536, 163840};
+// Strip width, prefetch depth, halo carriers and LDS cap of each variant.
+// Variants 0-3 keep their LDS ring within 64 KiB; variants 4-6 may use up to
+// the 160 KiB of a compute unit.  A variant whose ring would exceed its cap
+// for a given field count and working type falls back to variant 0.
+constexpr int kVariants = 7;
+constexpr int kTY[kVariants] = {6, 6, 14, 14, 10, 8, 16};
+constexpr int kD[kVariants] = {2, 4, 2, 4, 2, 2, 2};
+constexpr bool kEH[kVariants] = {false, false, false, false, false, true, true};
+constexpr int kLdsCap[kVariants] = {65536, 65536, 65536, 65536, 163840, 163840, 163840};
 
 template <typename T, typename C, int NF, int TY>
 constexpr int lds_bytes()
@@ -465,34 +518,49 @@ template <typename T, typename C, int NF, bool WS, bool WG, int V, int UPD>
 void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
     constexpr int TY = kTY[V], D = kD[V];
+    constexpr bool EH = kEH[V];
     if constexpr (lds_bytes<T, C, NF, TY>() <= kLdsCap[V]) {
         const Launch l = plan(g, TY);
-        hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, UPD>), dim3(l.grid), dim3(64 * (TY + 2)), 0,
-                           s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
+        hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, EH, UPD>), dim3(l.grid),
+                           dim3(64 * (EH ? TY : TY + 2)), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
     } else {
         go<T, C, NF, WS, WG, 0, UPD>(m, g, s);
     }
 }
 
-// Default variant per type pair, field count and output set, from sweeps on
-// MI355X at 4096 x 4096 x 64: 14-column strips (fewer halo waves per computed
-// column) wherever the registers allow 16 wavefronts; the six-field kernels
-// with FP64 arithmetic keep 6-column strips (their 150-190 registers allow 8
-// or 12 wavefronts per unit), except the FP32-storage adjoint, 11% faster in
-// 10-column strips.  Deeper prefetch (D = 4) measured no faster.
-// PW_MARCH_VARIANT=0..4 overrides the choice for sweeps.
-template <typename T, typename C, int NF, bool WS>
+// Default variant per type pair, field count, output set and update form,
+// from interleaved sweeps on MI355X at 4096 x 4096 x 64:
+//   * 14-column strips with halo waves wherever the registers allow 16
+//     wavefronts (HBM-bound FP64 and FP32 kernels, 16-bit forward kernels);
+//   * six-field kernels with FP64 arithmetic: 6-column strips (150-190
+//     registers allow 8 or 12 wavefronts per unit); for FP32 storage the
+//     adjoint in 10-column strips (11% faster) and the fused pass in
+//     8-column strips with edge waves (9% faster: its arithmetic sets the
+//     pace, and 8 computing waves keep all four SIMDs equally busy);
+//   * 16-bit storage: the adjoint and the accumulating update in 8-column
+//     strips with edge waves (8-10% faster), the bfloat16 fused pass in
+//     16-column strips with edge waves (5%).
+// Deeper prefetch (D = 4) measured no faster.  PW_MARCH_VARIANT=0..6
+// overrides the choice for sweeps.
+template <typename T, typename C, int NF, bool WS, int UPD>
 int default_variant()
 {
-    if (NF == 3 || sizeof(C) == 4) return 2;
-    if (sizeof(T) == 4 && !WS) return 4;
-    return 0;
+    if (NF == 6 && sizeof(C) == 8) {
+        if (sizeof(T) == 4) return WS ? 5 : 4;
+        return 0;
+    }
+    if (sizeof(T) == 2) {
+        if (NF == 6 && !WS) return 5;
+        if (NF == 3 && UPD == 1) return 5;
+        if (NF == 6 && std::is_same<T, bf16_t>::value) return 6;
+    }
+    return 2;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 {
-    int v = default_variant<T, C, NF, WS>();
+    int v = default_variant<T, C, NF, WS, UPD>();
     if (const char* e = std::getenv("PW_MARCH_VARIANT")) {
         const int q = std::atoi(e);
         if (q >= 0 && q < kVariants) v = q;
@@ -502,6 +570,8 @@ void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
     case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, s); break;
     case 3: go<T, C, NF, WS, WG, 3, UPD>(m, g, s); break;
     case 4: go<T, C, NF, WS, WG, 4, UPD>(m, g, s); break;
+    case 5: go<T, C, NF, WS, WG, 5, UPD>(m, g, s); break;
+    case 6: go<T, C, NF, WS, WG, 6, UPD>(m, g, s); break;
     default: go<T, C, NF, WS, WG, 0, UPD>(m, g, s); break;
     }
 }

@@ -20,7 +20,7 @@ import torch
 
 import oracle
 from paper_2010_01545_amd import inputs
-from _helpers import H, host_case, log, oracle_storage
+from _helpers import H, MARCH_VARIANTS, host_case, log, oracle_storage
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -108,7 +108,7 @@ def test_fused_separate_and_kernels_agree(pw, kind):
     old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
     try:
         os.environ["PW_MARCH_LX"] = "7"
-        for v in ("0", "1", "2", "3", "4"):
+        for v in MARCH_VARIANTS:
             os.environ["PW_MARCH_VARIANT"] = v
             f = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *c, H))
             for a, b in zip(results["direct"], f):

@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import oracle
-from _helpers import H, host_case, log, oracle_storage
+from _helpers import H, MARCH_VARIANTS, host_case, log, oracle_storage
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -113,7 +113,7 @@ def test_fused_equals_separate(pw, kernel):
         assert np.array_equal(interior(a), interior(b))
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
+@pytest.mark.parametrize("variant", MARCH_VARIANTS)
 def test_every_march_variant_matches_direct(pw, variant):
     fields, lams, coef = host_case(45, 31, 64, 49, lam_seed=50)
     st, sl = dev_f32(pw, as_f32(fields)), dev_f32(pw, as_f32(lams))

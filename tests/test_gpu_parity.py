@@ -20,7 +20,7 @@ import pytest
 import torch
 
 import oracle
-from _helpers import H, host_case, log, normwise, oracle_storage
+from _helpers import H, MARCH_VARIANTS, host_case, log, normwise, oracle_storage
 
 pytestmark = pytest.mark.gpu
 
@@ -187,13 +187,18 @@ def test_march_and_direct_agree_bitwise(pw, dtype):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
+@pytest.mark.parametrize("shape", [(45, 31, 64, 14), (12, 17, 40, 16)], ids=lambda s: "x".join(map(str, s[:3])))
+@pytest.mark.parametrize("variant", MARCH_VARIANTS)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_every_march_variant_matches_direct(pw, variant, dtype):
-    """Each strip-width / prefetch-depth variant of the x-marching kernel (and
-    a short march length, so several x-segments meet) gives the direct
-    kernel's bits, forward, adjoint and fused."""
-    fields, lams, coef = host_case(45, 31, 64, 14, lam_seed=64)
+def test_every_march_variant_matches_direct(pw, variant, dtype, shape):
+    """Each strip-width / prefetch-depth / halo-carrier variant of the
+    x-marching kernel (and a short march length, so several x-segments meet)
+    gives the direct kernel's bits, forward, adjoint and fused.  ny = 31 and
+    17 leave last strips one column and several columns narrower than every
+    strip width, and a one-column strip."""
+    nx, ny, nz, seed = shape
+    log("variant %s %s %s" % (variant, dtype, shape))
+    fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
     ref_f = run_fwd(pw, fields, coef, dtype, "direct", sentinel=False)
     ref_a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
     old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
@@ -268,7 +273,7 @@ def test_march_selection_limits(pw):
         assert np.array_equal(gi, r[halo:-halo, halo:-halo, halo:-halo])
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
+@pytest.mark.parametrize("variant", MARCH_VARIANTS)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_tall_columns_every_variant_matches_direct(pw, variant, dtype):
     """Columns taller than a wavefront are marched in z-chunks of 62 levels

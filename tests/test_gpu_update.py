@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from _helpers import H, host_case, log, oracle_storage
+from _helpers import H, MARCH_VARIANTS, host_case, log, oracle_storage
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -125,7 +125,7 @@ def test_update_f32_bound(pw, kernel, mode):
     check_layout(o)
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
+@pytest.mark.parametrize("variant", MARCH_VARIANTS)
 @pytest.mark.parametrize("mode", MODES)
 def test_update_march_variants_match_direct(pw, variant, mode):
     fields, base, coef = host_case(45, 31, 64, 67, lam_seed=68)
