@@ -26,7 +26,9 @@
 // engines to the inputs: with both directions on copy engines the runtime
 // now and then puts them on one engine, and the two transfers serialise
 // (measured at 4096 x 1024 x 64 FP64: 147-151 ms per call, or about 250 ms in
-// roughly one call of five; with the copy kernel 165-171 ms every call).
+// roughly one call of five, against 165-171 ms every call with the copy
+// kernel; on another kind of machine 210 ms, or about 457 ms in one call of
+// four, against 260-274 ms).
 #include <mutex>
 
 #include "../../include/pwadvect.h"
