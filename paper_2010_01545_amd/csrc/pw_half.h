@@ -41,8 +41,23 @@ __device__ inline _Float16 to_storage<_Float16>(double x)
     asm volatile("" : "+v"(f));
     return (_Float16)f;
 }
+// Device rounding of a binary32 to bfloat16 with the compute unit's own
+// conversion instruction: round to nearest even, the same bits as
+// bf16_bits_rne for every value but NaN (any quiet NaN), in one instruction
+// instead of the integer sequence.
+__device__ __forceinline__ bf16_t bf16_from_float(float f)
+{
+    bf16_t y;
+    y.bits = __builtin_bit_cast(unsigned short, (__bf16)f);
+    return y;
+}
 template <>
-__device__ inline bf16_t to_storage<bf16_t>(double x) { return bf16_t((float)x); }
+__device__ inline bf16_t to_storage<bf16_t>(double x)
+{
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return bf16_from_float(f);
+}
 
 // Rounding of an arithmetic-type result to the storage type, exactly once
 // from the arithmetic type's value.  For binary16 the float result is pinned
@@ -60,4 +75,10 @@ __device__ __forceinline__ _Float16 store_round<_Float16, float>(float x)
 {
     asm volatile("" : "+v"(x));
     return (_Float16)x;
+}
+template <>
+__device__ __forceinline__ bf16_t store_round<bf16_t, float>(float x)
+{
+    asm volatile("" : "+v"(x));
+    return bf16_from_float(x);
 }
