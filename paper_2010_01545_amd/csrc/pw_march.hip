@@ -230,7 +230,14 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
     static_assert(UPD == 0 || (NF == 3 && WS && !WG), "the update form is a forward-only epilogue");
     constexpr int NCOL = TY + 2;    // LDS slots
     constexpr int NT = NF / 3;      // field triples: 1 (winds) or 2 (winds + multipliers)
-    constexpr int U = D + 3;        // register ring length
+    // Register ring length and unroll of the plane loop (D + 3 planes are
+    // live).  An unroll of 6, a multiple of both LDS ring lengths, makes every
+    // LDS slot index a compile-time constant and saves the address arithmetic:
+    // 2-5% for the narrow-storage kernels with halo waves, whose instruction
+    // issue sets their pace.  The HBM-bound FP64-storage kernels measured 2%
+    // slower with it and the register-bound edge-wave kernels spill, so they
+    // keep the unroll of D + 3.
+    constexpr int U = (D + 3 <= 6 && sizeof(T) < 8 && !EH) ? 6 : D + 3;
     constexpr int NR = NF + (UPD == 1 ? 3 : 0);   // ring rows: fields, then base arrays
     using W = work_t<T, C>;
     __shared__ W s_uw[2 * NT][2][NCOL][NZ];
@@ -344,11 +351,11 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int t = f / 3;
-            if (f % 3 == 0) s_uw[2 * t][i0 & 1][slot][lane] = R[f][1];
-            if (f % 3 == 2) s_uw[2 * t + 1][i0 & 1][slot][lane] = R[f][1];
+            if (f % 3 == 0) s_uw[2 * t][0][slot][lane] = R[f][1];
+            if (f % 3 == 2) s_uw[2 * t + 1][0][slot][lane] = R[f][1];
             if (f % 3 == 1) {
-                s_v[t][i0 % 3][slot][lane] = R[f][1];
-                s_v[t][(i0 + 1) % 3][slot][lane] = R[f][2];
+                s_v[t][0][slot][lane] = R[f][1];
+                s_v[t][1][slot][lane] = R[f][2];
             }
         }
         if (halo) {
@@ -356,27 +363,36 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
             for (int f = 0; f < NF; ++f) {
                 const int t = f / 3;
                 const W h1 = mask(f, widen<T, W>(H[f][1]));
-                if (f % 3 == 0) s_uw[2 * t][i0 & 1][hslot][lane] = h1;
-                if (f % 3 == 2) s_uw[2 * t + 1][i0 & 1][hslot][lane] = h1;
+                if (f % 3 == 0) s_uw[2 * t][0][hslot][lane] = h1;
+                if (f % 3 == 2) s_uw[2 * t + 1][0][hslot][lane] = h1;
                 if (f % 3 == 1) {
-                    s_v[t][i0 % 3][hslot][lane] = h1;
-                    s_v[t][(i0 + 1) % 3][hslot][lane] = mask(f, widen<T, W>(H[f][2]));
+                    s_v[t][0][hslot][lane] = h1;
+                    s_v[t][1][hslot][lane] = mask(f, widen<T, W>(H[f][2]));
                 }
             }
         }
     }
     __syncthreads();
 
+    // Operands shared by consecutive steps, so each is shifted once: the
+    // u-type F(p-1, j, k+1) is the previous step's F(p, j, k+1) of the centre,
+    // the w-type F(p, j, k-1) the previous step's F(p+1, j, k-1).
+    W zcar[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) zcar[f] = f % 3 == 0 ? above(R[f][0]) : f % 3 == 2 ? below(R[f][1]) : W(0);
+
+    // LDS slots count planes from the segment start: u/w-type plane q in slot
+    // (q - i0) % 2, v-type in (q - i0) % 3
     for (int pb = i0; pb < i1; pb += U) {
-        const int vb = pb % 3;
+        const int rel = U % 6 == 0 ? 0 : pb - i0;
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const int p = pb + s;
             if (p >= i1) break;  // uniform over the workgroup
             const int rm = s % U, rc = (s + 1) % U, rq0 = (s + 2) % U, rq1 = (s + 3) % U;
             const int rnew = (s + D + 2) % U;
-            const int pu = p & 1;
-            const int v0 = (vb + s) % 3, v1 = (vb + s + 1) % 3, v2 = (vb + s + 2) % 3;
+            const int pu = (rel + s) & 1;
+            const int v0 = (rel + s) % 3, v1 = (rel + s + 1) % 3, v2 = (rel + s + 2) % 3;
 
             // prefetch plane p + D + 1
 #pragma unroll
@@ -403,13 +419,13 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
                     q.c = R[f][rc];
                     q.xm = R[f][rm];
                     q.xp = R[f][rq0];
-                    q.zm = below(q.c);
+                    q.zm = f % 3 == 2 ? zcar[f] : below(q.c);
                     q.zp = above(q.c);
                     if (f % 3 == 0) {            // u-type
                         q.ym = s_uw[2 * t][pu][slot - 1][lane];
                         q.yp = s_uw[2 * t][pu][slot + 1][lane];
                         q.d1 = carry[f];         // F(p-1, j+1)
-                        q.d2 = above(q.xm);      // F(p-1, j, k+1)
+                        q.d2 = zcar[f];          // F(p-1, j, k+1)
                     } else if (f % 3 == 1) {     // v-type
                         q.ym = carry[f];         // F(p, j-1)
                         q.yp = s_v[t][v0][slot + 1][lane];
@@ -436,6 +452,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
                 for (int f = 0; f < NF; ++f) {
                     if (f % 3 == 0) carry[f] = st[f].yp;  // becomes F((p+1)-1, j+1)
                     if (f % 3 == 1) carry[f] = st[f].d1;  // becomes F(p+1, j-1)
+                    if (f % 3 == 0) zcar[f] = st[f].zp;   // becomes F((p+1)-1, j, k+1)
+                    if (f % 3 == 2) zcar[f] = st[f].d1;   // becomes F(p+1, j, k-1)
                 }
             }
 
