@@ -301,3 +301,39 @@ def test_tall_columns_every_variant_matches_direct(pw, variant, dtype):
         assert not np.any(np.isnan(col))
         assert np.all(col[:, :, :H] == 0) and np.all(col[:, :, -H:] == 0)
         assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[:, :H]))
+
+
+@pytest.mark.parametrize("variant", ["5", "6"])
+@pytest.mark.parametrize("halo", [1, 3])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_edge_wave_variants_other_halos(pw, variant, halo, dtype):
+    """The edge-wave variants address their extra halo column through the
+    storage geometry: with halo 1 and 3 (and a last strip one column and
+    several columns short of the strip width) the fused pass gives the direct
+    kernel's bits."""
+    log("edge-wave variant %s halo %d %s" % (variant, halo, dtype))
+    fields, lams, coef = host_case(11, 23, 40, 17, lam_seed=67)
+    tzc1, tzc2, tcx, tcy = coef
+    st = [pw.pad_periodic(t, halo) for t in to_dev(fields, dtype)]
+    sl = [pw.pad_periodic(t, halo) for t in to_dev(lams, dtype)]
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    res = {}
+    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
+    os.environ["PW_MARCH_VARIANT"] = variant
+    os.environ["PW_MARCH_LX"] = "5"
+    try:
+        for kernel in ("direct", "march"):
+            prev = pw.set_kernel(kernel)
+            try:
+                res[kernel] = [o.cpu().numpy() for o in pw.fwd_adj(*st, *sl, t1, t2, tcx, tcy, halo)]
+            finally:
+                pw.set_kernel(prev)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    inner_h = lambda a: a[halo:-halo, halo:-halo, halo:-halo]
+    for a, b in zip(res["direct"], res["march"]):
+        assert np.array_equal(inner_h(a), inner_h(b))
