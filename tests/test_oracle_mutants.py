@@ -2,10 +2,12 @@
 
 Each mutant is a plausible slip in pw_oracle.c (a sign, a face offset, a
 transposed operand, a level range, a dropped or misdirected adjoint term, a
-wrong fold), applied to a temporary copy of the source, compiled on the CPU
-with the oracle's flags and routed in with ``oracle.use_library``.  The pins
-of test_oracle_pins, test_oracle_adjoint and test_oracle_update must fail for
-every mutant, and pass for the unmodified copy built the same way.
+wrong fold, a dropped, doubled or signed term of the error magnitudes, an
+abs mode left switched on), applied to a temporary copy of the source,
+compiled on the CPU with the oracle's flags and routed in with
+``oracle.use_library``.  The pins of test_oracle_pins, test_oracle_adjoint,
+test_oracle_update and test_oracle_magnitudes must fail for every mutant, and
+pass for the unmodified copy built the same way.
 """
 import os
 import subprocess
@@ -13,6 +15,7 @@ import subprocess
 import pytest
 
 import test_oracle_adjoint as adj_pins
+import test_oracle_magnitudes as mag_pins
 import test_oracle_pins as fwd_pins
 import test_oracle_update as upd_pins
 
@@ -38,6 +41,13 @@ PINS = [
     (adj_pins.test_fold_is_transpose_of_pad, {}),
     (upd_pins.test_update_of_hand_values, {}),
     (upd_pins.test_euler_step_energy, {}),
+    (mag_pins.test_forward_magnitude_hand_values, {}),
+    (mag_pins.test_adjoint_magnitude_hand_values, {}),
+    (mag_pins.test_magnitudes_ignore_every_sign, {}),
+    (mag_pins.test_triangle_inequality_and_equality, {}),
+    (mag_pins.test_magnitude_scaling, {}),
+    (mag_pins.test_abs_call_leaves_signed_adjoint_alone, {}),
+    (mag_pins.test_magnitudes_never_read_z_halo, {}),
 ]
 
 # (name, text in pw_oracle.c, replacement, which occurrence (0-based))
@@ -64,6 +74,23 @@ MUTANTS = [
     ("adj_misdirected_target", "term(gu, SIDX(i, j + 1, k), gv, c, gv, SIDX(i + 1, j, k), u, v, v, l, -tcy);",
      "term(gu, SIDX(i, j + 1, k), gv, c, gv, SIDX(i, j + 1, k), u, v, v, l, -tcy);", 0),
     ("fold_assigns", "g[SIDX(ii, jj, k)] += g[s];", "g[SIDX(ii, jj, k)] = g[s];", 0),
+    # rounding-error magnitudes T(c) (the scale of every reduced-precision bound)
+    ("abs_su_tzc2_dropped", "if (k < nz - 1)\n                    t += fabs(tzc2[k]) * A(u, i, j, k + 1)",
+     "if (k < 0)\n                    t += fabs(tzc2[k]) * A(u, i, j, k + 1)", 0),
+    ("abs_sv_x_doubled", "t = ax * (A(v, i - 1, j, k)", "t = 2 * ax * (A(v, i - 1, j, k)", 0),
+    ("abs_sw_tzc1_doubled", "t += fabs(tzc1[k]) * A(w, i, j, k - 1)", "t += 2 * fabs(tzc1[k]) * A(w, i, j, k - 1)", 0),
+    ("abs_su_top_keeps_tzc2", "if (k < nz - 1)\n                    t += fabs(tzc2[k]) * A(u, i, j, k + 1)",
+     "if (k < nz)\n                    t += fabs(tzc2[k]) * A(u, i, j, k + 1)", 0),
+    ("abs_field_not_abs", "#define A(F, ii, jj, kk) fabs(F[SIDX(ii, jj, kk)])",
+     "#define A(F, ii, jj, kk) (F[SIDX(ii, jj, kk)])", 0),
+    ("abs_coef_not_abs", "double ax = fabs(tcx), ay = fabs(tcy);", "double ax = tcx, ay = fabs(tcy);", 0),
+    ("abs_face_sum_inside", "(A(w, i, j, k) + A(w, i, j, k - 1))",
+     "fabs(w[SIDX(i, j, k)] + w[SIDX(i, j, k - 1)])", 0),
+    ("abs_adj_lambda_signed", "lam = fabs(lam);", "", 0),
+    ("abs_adj_field_signed", "B = fabs(B);", "", 0),
+    ("abs_adj_dropped_fabs_coef", "coef = fabs(coef);", "", 0),
+    ("abs_mode_left_set", "pw_oracle_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, nx, ny, nz, h, gu, gv, gw);\n    g_abs_mode = 0;",
+     "pw_oracle_adj(u, v, w, lu, lv, lw, tzc1, tzc2, tcx, tcy, nx, ny, nz, h, gu, gv, gw);", 0),
 ]
 
 
