@@ -17,9 +17,14 @@ and the CPU oracle timed on a bounded sample of the same workload.
 Also printed, as context: the host-resident offload (fields in pinned host
 memory, pipelined x-slab transfers, pw_advect_fwd_host) at 4096x1024x64.
 
+Also printed: the library's plain streaming copy over the headline's own
+arrays (the achievable-bandwidth reference, timed interleaved with the
+kernels), the paths at 1024x1024x64 (the precision workload), and the
+cache-resident 256x256x64 forward and fused pass.
+
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
        [--kernel auto|direct|march] [--no-cpu-baseline] [--no-offload]
-       [--paths-reps R]
+       [--paths-reps R] [--no-paths] [--no-medium] [--only PATH:DTYPE|copy|copy3|copy6]
 """
 import argparse
 import hashlib
@@ -152,9 +157,70 @@ def path_record(path, esize, cells, times_ms):
     }
 
 
-def cpu_baseline(nx, ny, nz, seed, budget_s=12.0, planes=32):
-    """Oracle forward + scatter adjoint (single thread, FP64) on x-planes
-    0..planes-1 of the workload, repeated until budget_s of oracle time."""
+COPY_BLOCKS = (0, 1024, 2048, 4096)   # launch shapes of the streaming copy (0: one pass)
+
+
+def copy_reference(pw, torch, g, reps=5):
+    """The library's plain streaming copy (pw_stream_copy) over the very
+    arrays the headline kernel uses (same placement in HBM): 6 arrays read and
+    6 written (the fused pass's streams: u, v, w, lu, lv, lw -> su .. gw) and
+    3 + 3 (the forward's).  Each launch shape is timed; the fastest is the
+    achievable-bandwidth reference.  Timed interleaved with the FP64 fused and
+    forward kernels on the same arrays, so that their ratio compares like with
+    like."""
+    nbytes = g.f[0].numel() * g.f[0].element_size()
+    rec = {"kernel": "pw_stream_copy: 16-byte loads and stores, every thread reads its unit of each source "
+                     "then writes each destination; storage arrays of %d bytes" % nbytes}
+    for tag, src, dst, path in (("6R6W", g.f + g.l, g.s + g.g, "fused"), ("3R3W", g.f, g.s, "fwd")):
+        shapes = {}
+        for b in COPY_BLOCKS:
+            pw.stream_copy(src, dst, b)
+            ms = time_launches(torch, lambda: pw.stream_copy(src, dst, b), reps)
+            shapes["blocks_%d" % b] = {"ms": sum(ms) / len(ms),
+                                        "GBps": 2 * len(src) * nbytes / (sum(ms) / len(ms) * 1e-3) / 1e9}
+        best = min(shapes, key=lambda k: shapes[k]["ms"])
+        b = int(best.split("_")[1])
+        # interleaved: copy, kernel, copy, kernel ...
+        tc, tk = [], []
+        for _ in range(reps):
+            tc += time_launches(torch, lambda: pw.stream_copy(src, dst, b), 1)
+            tk += time_launches(torch, lambda: g.launch(pw, path), 1)
+        mc, mk = sum(tc) / len(tc), sum(tk) / len(tk)
+        rec[tag] = {"ms": mc, "GBps": 2 * len(src) * nbytes / (mc * 1e-3) / 1e9, "blocks": b,
+                    "launch_shapes": shapes,
+                    "interleaved_%s_f64_ms" % path: mk,
+                    "%s_f64_time_fraction_of_copy" % path: mc / mk}
+        # torch's device copy of the same arrays, for comparison
+        step = lambda: [d.copy_(x) for d, x in zip(dst, src)]
+        step()
+        t = time_launches(torch, step, reps)
+        rec[tag]["torch_copy_GBps"] = 2 * len(src) * nbytes / (sum(t) / len(t) * 1e-3) / 1e9
+    return rec
+
+
+def host_threads():
+    """Host threads for the CPU baseline: OMP_NUM_THREADS when set, else the
+    usable cores, at most 16 (one GPU's share of its host)."""
+    usable = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    n = int(os.environ.get("OMP_NUM_THREADS", usable))
+    return max(1, min(n, usable, 16)), usable
+
+
+def cpu_baseline(nx, ny, nz, seed, budget_s=8.0, planes=32, slab_planes=8):
+    """The oracle (FP64 C, unmodified) timed on the host on bounded samples of
+    the workload:
+      * value: forward + scatter adjoint (the fused step's work) on all host
+        threads at once, each running the single-threaded oracle on its own
+        x-slab of slab_planes planes (slab t starts at plane t * slab_planes;
+        its x halo planes are the true neighbour planes, y is periodic), for
+        about budget_s of wall time; ctypes releases the GIL during each call;
+      * single_thread: the same on x-planes 0..planes-1 on one thread;
+      * fwd_openmp: the OpenMP build of the oracle's forward on that slab."""
+    import threading
     import numpy as np
     import oracle
     from paper_2010_01545_amd import inputs
@@ -165,44 +231,79 @@ def cpu_baseline(nx, ny, nz, seed, budget_s=12.0, planes=32):
         s = np.pad(a, ((0, 0), (h, h), (0, 0)), mode="wrap")
         return np.ascontiguousarray(np.pad(s, ((0, 0), (0, 0), (h, h))))
 
-    f = [slab(a) for a in inputs.winds(seed, nx, ny, nz, x0=-h, x1=planes + h)]
-    lam = [slab(a) for a in inputs.multipliers_uniform(seed, nx, ny, nz, x0=-h, x1=planes + h)]
-    cells = planes * ny * nz
-    spent, reps = 0.0, 0
-    while spent < budget_s:
-        t0 = time.perf_counter()
+    def make(x0, n):
+        f = [slab(a) for a in inputs.winds(seed, nx, ny, nz, x0=x0 - h, x1=x0 + n + h)]
+        lam = [slab(a) for a in inputs.multipliers_uniform(seed, nx, ny, nz, x0=x0 - h, x1=x0 + n + h)]
+        return f, lam
+
+    def step(f, lam):
         oracle.fwd(*f, tzc1, tzc2, tcx, tcy, h)
         oracle.adj(*f, *lam, tzc1, tzc2, tcx, tcy, h)
-        spent += time.perf_counter() - t0
-        reps += 1
-    fused = cells * reps / spent / 1e9
-    # the forward alone with the OpenMP build of the same source; its thread
-    # count is OMP_NUM_THREADS when set, else one per usable core
-    usable = os.cpu_count() or 1
-    try:
-        usable = len(os.sched_getaffinity(0))
-    except AttributeError:
-        pass
-    threads = int(os.environ.get("OMP_NUM_THREADS", usable))
+
+    threads, usable = host_threads()
+    # all threads at once, each on its own slab
+    data = [None] * threads
+    reps = [0] * threads
+    gate = threading.Barrier(threads + 1)
+    deadline = [0.0]
+
+    def worker(t):
+        data[t] = make(t * slab_planes, slab_planes)
+        gate.wait()
+        while True:
+            step(*data[t])
+            reps[t] += 1
+            if time.perf_counter() >= deadline[0]:
+                break
+
+    pool = [threading.Thread(target=worker, args=(t,)) for t in range(threads)]
+    for th in pool:
+        th.start()
+    t0 = time.perf_counter()
+    deadline[0] = t0 + 1e9
+    gate.wait()
+    t0 = time.perf_counter()
+    deadline[0] = t0 + budget_s
+    for th in pool:
+        th.join()
+    wall = time.perf_counter() - t0
+    slab_cells = slab_planes * ny * nz
+    multi = sum(reps) * slab_cells / wall / 1e9
+    del data
+
+    # one thread
+    f, lam = make(0, planes)
+    cells = planes * ny * nz
+    spent, n1 = 0.0, 0
+    while spent < budget_s:
+        t1 = time.perf_counter()
+        step(f, lam)
+        spent += time.perf_counter() - t1
+        n1 += 1
+    single = cells * n1 / spent / 1e9
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    t0 = time.perf_counter()
+    t1 = time.perf_counter()
     nrep = 0
-    while time.perf_counter() - t0 < 2.0:
+    while time.perf_counter() - t1 < 2.0:
         oracle.fwd(*f, tzc1, tzc2, tcx, tcy, h, threaded=True)
         nrep += 1
-    fwd_omp = cells * nrep / (time.perf_counter() - t0) / 1e9
+    fwd_omp = cells * nrep / (time.perf_counter() - t1) / 1e9
     return {
-        "value": fused, "unit": "Gcells/s", "cores": 1, "kind": "oracle",
-        "sample": "oracle fwd + scatter adjoint, FP64, single thread, on x-planes 0..%d of the "
-                  "%dx%dx%d grid (%d cells) repeated %d times (%.1f s)"
-                  % (planes - 1, nx, ny, nz, cells, reps, spent),
+        "value": multi, "unit": "Gcells/s", "cores": threads, "kind": "oracle",
+        "sample": "oracle fwd + scatter adjoint, FP64, unmodified single-threaded C, run concurrently by %d "
+                  "threads, each on its own %d-plane x-slab of the %dx%dx%d grid (slabs at planes 0, %d, ...; "
+                  "%d cells each), %d slab steps in %.1f s"
+                  % (threads, slab_planes, nx, ny, nz, slab_planes, slab_cells, sum(reps), wall),
+        "single_thread": {"value": single, "unit": "Gcells/s", "cores": 1,
+                          "sample": "the same on x-planes 0..%d (%d cells), %d steps in %.1f s"
+                                    % (planes - 1, cells, n1, spent)},
         "fwd_openmp": {"value": fwd_omp, "unit": "Gcells/s", "threads": threads,
-                       "sample": "oracle forward, OpenMP build, same slab"},
+                       "sample": "oracle forward only, OpenMP build, x-planes 0..%d" % (planes - 1)},
         "host": {"cpu_model": model, "usable_cores": usable},
     }
 
@@ -236,27 +337,20 @@ def offload_measure(pw, torch, reps=4, chunk=64):
         return ev[0].elapsed_time(ev[1]) / n
 
     run = lambda: pw.fwd_host(*host_in, g.t1, g.t2, g.tcx, g.tcy, h, *host_out, chunk, ws)
-    # copy-out modes: the library's copy kernel (default for pinned outputs)
-    # and the runtime's copies; both warmed, then timed call by call in
-    # alternation so that neither profits from the other's warm-up
-    old = os.environ.get("PW_OFFLOAD_COPY_OUT")
-    calls = {"kernel": [], "runtime": []}
-    try:
-        for mode in calls:
-            os.environ["PW_OFFLOAD_COPY_OUT"] = mode
+    # copy-out modes: the runtime's copies (the default) and the library's
+    # copy kernel; both warmed, then timed call by call in alternation so
+    # that neither profits from the other's warm-up
+    calls = {"runtime": [], "kernel": []}
+    for mode in calls:
+        with pw.tuning(copy_out=mode):
             run()
-            torch.cuda.synchronize()
-        for _ in range(reps):
-            for mode in calls:
-                os.environ["PW_OFFLOAD_COPY_OUT"] = mode
+        torch.cuda.synchronize()
+    for _ in range(reps):
+        for mode in calls:
+            with pw.tuning(copy_out=mode):
                 calls[mode].append(timed(run, 1))
-    finally:
-        if old is None:
-            os.environ.pop("PW_OFFLOAD_COPY_OUT")
-        else:
-            os.environ["PW_OFFLOAD_COPY_OUT"] = old
     med = lambda v: sorted(v)[len(v) // 2]
-    t_off, t_off_rt = med(calls["kernel"]), med(calls["runtime"])
+    t_off, t_off_k = med(calls["runtime"]), med(calls["kernel"])
     t_h2d = timed(lambda: [d.copy_(hsrc, non_blocking=True) for d, hsrc in zip(g.f, host_in)], reps)
     t_d2h = timed(lambda: [o.copy_(d, non_blocking=True) for o, d in zip(host_out, g.s)], reps)
     t_k = timed(lambda: g.launch(pw, "fwd"), reps)
@@ -267,10 +361,11 @@ def offload_measure(pw, torch, reps=4, chunk=64):
         "cells": cells,
         "gcells_per_s_incl_transfers": cells / (t_off * 1e-3) / 1e9,
         "ms_pipelined": t_off,
-        "ms_pipelined_runtime_copy_out": t_off_rt,
+        "ms_pipelined_copy_kernel_out": t_off_k,
         "ms_per_call": {k: [round(x, 2) for x in v] for k, v in calls.items()},
         "ms_copy_in_alone": t_h2d, "ms_copy_out_alone": t_d2h, "ms_kernel_alone": t_k,
         "copy_in_GBps": nbytes / (t_h2d * 1e-3) / 1e9, "copy_out_GBps": nbytes / (t_d2h * 1e-3) / 1e9,
+        "ms_serial_sum": t_h2d + t_d2h + t_k,
         "overlap": (t_h2d + t_d2h + t_k) / t_off,
         "ideal_ms": max(t_h2d, t_d2h),
         "bytes_each_way": nbytes,
@@ -293,7 +388,9 @@ def main():
     ap.add_argument("--no-offload", action="store_true")
     ap.add_argument("--no-medium", action="store_true",
                     help="skip the cache-resident 256x256x64 record (its launches share the kernels' names)")
-    ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64")
+    ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64, "
+                    "or the streaming copy of 3 or 6 storage arrays (copy3, copy6)")
+    ap.add_argument("--copy-blocks", type=int, default=0, help="launch shape of --only copy3/copy6")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -324,6 +421,17 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy calibration done (%d bytes per launch each way)" % n)
         return
+    if args.only in ("copy3", "copy6"):
+        # the streaming copy reference over the headline's storage arrays
+        g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True)
+        n = int(args.only[-1])
+        src, dst = (g.f + g.l)[:n], (g.s + g.g)[:n]
+        torch.cuda.synchronize()
+        for _ in range(args.warmup + args.steps):
+            pw.stream_copy(src, dst, args.copy_blocks)
+        torch.cuda.synchronize()
+        log("bench: profile run of %s done" % args.only)
+        return
     if args.only:
         path, dt = args.only.split(":")
         st_dt = {"f64": torch.float64, "f16": torch.float16, "bf16": torch.bfloat16}.get(dt, torch.float32)
@@ -349,6 +457,12 @@ def main():
     wall = time.perf_counter() - t0
     head = path_record("fused", 8, cells, times)
     log("bench: fused f64 %.2f ms/launch, %.1f Gcells/s" % (head["ms_avg"], head["gcells_per_s"]))
+
+    # achievable-bandwidth reference on the same arrays
+    copy_ref = copy_reference(pw, torch, g)
+    log("bench: stream copy 6R6W %.0f GB/s (fused at %.3f of its speed), 3R3W %.0f GB/s (fwd at %.3f)" % (
+        copy_ref["6R6W"]["GBps"], copy_ref["6R6W"]["fused_f64_time_fraction_of_copy"],
+        copy_ref["3R3W"]["GBps"], copy_ref["3R3W"]["fwd_f64_time_fraction_of_copy"]))
 
     paths = {"fused_f64": head}
     if not args.no_paths:
@@ -391,22 +505,6 @@ def main():
             for v in ("_f32", "_f32f64", "_f16", "_bf16"):
                 paths[p + v]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + v]["ms_avg"]
 
-    # achievable-bandwidth reference: torch's device copy (__amd_rocclr_copyBuffer)
-    # of the same storage arrays, 6 reads + 6 writes (the fused kernel's
-    # streams) and 3 + 3 (the forward's)
-    g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True)
-    storage_bytes = g.f[0].numel() * 8
-    copy_ref = {"kernel": "torch copy_ of %d-byte storage arrays" % storage_bytes}
-    for tag, src, dst in (("6R6W", g.f + g.l, g.s + g.g), ("3R3W", g.f, g.s)):
-        step = lambda: [d.copy_(x) for d, x in zip(dst, src)]
-        step()
-        t = time_launches(torch, step, 5)
-        ms = sum(t) / len(t)
-        copy_ref[tag] = {"ms": ms, "GBps": 2 * len(src) * storage_bytes / (ms * 1e-3) / 1e9}
-    del g
-    torch.cuda.empty_cache()
-    log("bench: copy reference 6R6W %.0f GB/s, 3R3W %.0f GB/s" % (copy_ref["6R6W"]["GBps"], copy_ref["3R3W"]["GBps"]))
-
     # 256x256x64 (the medium workload): the forward's six FP64 arrays (221 MB)
     # fit the 256 MB Infinity Cache, so its rate is not an HBM figure
     medium = None
@@ -421,6 +519,24 @@ def main():
             medium[p] = path_record(p, 8, cm, time_launches(torch, lambda: g.launch(pw, p), 100))
         del g
         torch.cuda.empty_cache()
+
+    # 1024x1024x64 (the precision workload): GB/s of the FP64 and FP32 paths
+    precision = None
+    if not args.no_paths:
+        wp = inputs.WORKLOADS["precision"]
+        cp = wp["nx"] * wp["ny"] * wp["nz"]
+        precision = {"workload": "precision %dx%dx%d, 20 launches each" % (wp["nx"], wp["ny"], wp["nz"])}
+        for tag, dt, esz in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            g = Grid(pw, torch, wp["nx"], wp["ny"], wp["nz"], h, dt, wp["seed"], True)
+            for p in ("fwd", "adj", "fused"):
+                g.launch(pw, p)
+                precision[p + "_" + tag] = path_record(p, esz, cp, time_launches(torch, lambda: g.launch(pw, p), 20))
+            del g
+            torch.cuda.empty_cache()
+        for p in ("fwd", "adj", "fused"):
+            precision[p + "_f32"]["speedup_vs_f64"] = precision[p + "_f64"]["ms_avg"] / precision[p + "_f32"]["ms_avg"]
+        log("bench: 1024^2 fwd f64 %.0f GB/s, f32 %.0f GB/s" % (precision["fwd_f64"]["alg_GBps"],
+                                                             precision["fwd_f32"]["alg_GBps"]))
 
     kname = "fused_f64"
     traffic = measured_traffic(kname, args.workload)
@@ -443,14 +559,15 @@ def main():
         "roofline": roofline,
         "paths": paths,
         "copy_reference": copy_ref,
+        "precision_workload": precision,
         "medium_cache_resident": medium,
         "source_hash": kernel_source_hash(),
     }
     if not args.no_offload:
         log("bench: host-resident offload at 4096x1024x64")
         out["offload"] = offload_measure(pw, torch)
-        log("bench: offload %.1f ms pipelined, %.1f with runtime copies out (in %.1f, kernel %.1f, out %.1f)" % (
-            out["offload"]["ms_pipelined"], out["offload"]["ms_pipelined_runtime_copy_out"],
+        log("bench: offload %.1f ms pipelined, %.1f with the copy kernel out (in %.1f, kernel %.1f, out %.1f)" % (
+            out["offload"]["ms_pipelined"], out["offload"]["ms_pipelined_copy_kernel_out"],
             out["offload"]["ms_copy_in_alone"],
             out["offload"]["ms_kernel_alone"], out["offload"]["ms_copy_out_alone"]))
     if not args.no_cpu_baseline:

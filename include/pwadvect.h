@@ -24,9 +24,11 @@
  *
  * Every pointer is a device pointer (hipMalloc / torch device memory) owned by
  * the caller, except the host field arrays of pw_advect_fwd_host.  The library
- * allocates no memory; it keeps the kernel selection, the last error text and,
- * once pw_advect_fwd_host has run on a device, two copy streams and a few
- * events for that device.  It is thread-safe apart from pw_set_kernel.
+ * allocates no memory and reads no environment variables.  The state it keeps
+ * is per thread (the tuning knobs of pw_set_tuning and the last error text)
+ * or created once per device (two copy streams and a few events, from the
+ * first pw_advect_fwd_host call on that device until the process ends), so
+ * every call is thread-safe.
  *
  * ---------------------------------------------------------------- semantics
  * Levels follow Listing 1: Fortran k = 2..z_size is interior k = 1..nz-1.
@@ -58,7 +60,9 @@
  *   PW_ERR_ALIGN        a pointer is not aligned to its element type
  *   PW_ERR_SIZE         n + 2*halo overflows int, or a storage byte count
  *                       overflows int64
- *   PW_ERR_UNSUPPORTED  the selected kernel cannot run this shape
+ *   PW_ERR_UNSUPPORTED  the selected kernel cannot run this shape (the
+ *                       x-marching kernels need halo <= 32, 16-byte aligned
+ *                       arrays and columns of fewer than 2^30 bytes)
  *   PW_ERR_HIP          the HIP runtime reported an error at launch
  */
 #ifndef PWADVECT_H
@@ -94,11 +98,32 @@ enum {
     PW_ERR_HIP = -6
 };
 
-/* Kernel selection (process-wide; see pw_set_kernel). */
+/* Kernel families (tuning knob PW_TUNE_KERNEL). */
 enum {
     PW_KERNEL_AUTO = 0,   /* x-marching kernel where it applies, else direct */
     PW_KERNEL_DIRECT = 1, /* one thread per storage level, any nz >= 2 */
-    PW_KERNEL_MARCH = 2   /* x-marching, LDS-staged kernel; halo <= 32 */
+    PW_KERNEL_MARCH = 2   /* x-marching, LDS-staged kernel (see PW_ERR_UNSUPPORTED) */
+};
+
+/* Tuning knobs (pw_set_tuning).  None changes a result: every kernel family
+ * and variant gives the same bits.  Defaults in brackets. */
+enum {
+    PW_TUNE_KERNEL = 0,        /* kernel family, PW_KERNEL_* [PW_KERNEL_AUTO] */
+    PW_TUNE_MARCH_VARIANT = 1, /* x-marching variant 0..PW_MARCH_VARIANTS-1 (strip
+                                  width, prefetch depth, halo carriers), or -1 for
+                                  the measured default of each storage/arithmetic
+                                  type and output set [-1] */
+    PW_TUNE_MARCH_LX = 2,      /* x-planes per marching workgroup, or 0 to choose
+                                  from the grid [0] */
+    PW_TUNE_COPY_OUT = 3       /* how pw_advect_fwd_host returns the source terms,
+                                  PW_COPY_OUT_* [PW_COPY_OUT_RUNTIME] */
+};
+enum { PW_MARCH_VARIANTS = 7 };
+enum {
+    PW_COPY_OUT_RUNTIME = 0, /* the HIP runtime's device-to-host copies */
+    PW_COPY_OUT_KERNEL = 1   /* a copy kernel writing pinned host outputs that are
+                                mapped into the device's address space (other
+                                outputs still use the runtime's copies) */
 };
 
 /*
@@ -180,10 +205,10 @@ int pw_advect_fwd_update(const void *u, const void *v, const void *w,
  * there, and work queued there afterwards sees every result.  Kernels run on
  * `stream`; the copies use two streams the library creates once per device and
  * keeps until the process ends (default priority).  Inputs go in through the
- * runtime's host-to-device copies.  Outputs that are pinned host memory mapped
- * into the device's address space are written back by a copy kernel of the
- * library (PW_OFFLOAD_COPY_OUT=runtime in the environment selects the
- * runtime's copies instead); other outputs by the runtime's copies.  Concurrent calls are
+ * runtime's host-to-device copies, outputs come back through the runtime's
+ * device-to-host copies unless the calling thread set PW_TUNE_COPY_OUT to
+ * PW_COPY_OUT_KERNEL (then pinned outputs mapped into the device's address
+ * space are written by a copy kernel of the library).  Concurrent calls are
  * serialized while they are queued.  Results are identical to pw_advect_fwd on
  * the same data.  Errors as for pw_advect_fwd; PW_ERR_ARG if a field array is
  * device memory, PW_ERR_SIZE if the workspace is too small.
@@ -230,10 +255,33 @@ int pw_fill_uniform(void *storage, int nx, int ny, int nz, int halo,
                     int dtype, void *stream);
 
 /*
- * Selects the kernel family used by the three advection calls, for every
- * thread of the process (set it before concurrent use).  Returns the
- * previous selection, or PW_ERR_ARG for an unknown value.
+ * Measurement utility (not part of the scheme): one launch of a plain
+ * streaming copy kernel that copies src[q] to dst[q] for q < narrays, each
+ * `bytes` long, with 16-byte accesses, every thread reading its 16-byte units
+ * of all sources before writing them to all destinations.  It moves the
+ * streams of the advection calls over arrays of the same size (3 arrays: the
+ * forward's 3 reads and 3 writes; 6 arrays: those of pw_advect_fwd_adj) and
+ * so is the achievable-bandwidth reference their HBM rate is read against.
+ * src and dst are HOST arrays of narrays device pointers, each 16-byte
+ * aligned; bytes must be a multiple of 16; 1 <= narrays <= 8; no destination
+ * may overlap any array.  blocks = 0 launches one 256-thread workgroup per
+ * 4 KiB of each array (each thread copies one 16-byte unit per array), blocks
+ * > 0 launches that many workgroups striding over the arrays.  Asynchronous
+ * on `stream`.  Errors: PW_ERR_ARG, PW_ERR_ALIGN, PW_ERR_ALIAS, PW_ERR_HIP.
  */
+int pw_stream_copy(const void *const *src, void *const *dst, int narrays, size_t bytes, int blocks,
+                   void *stream);
+
+/*
+ * Sets tuning knob `knob` (PW_TUNE_*) of the calling thread to `value`: the
+ * setting applies to the calls this thread makes afterwards and to no other
+ * thread.  Returns PW_OK, or PW_ERR_ARG (nothing changed) for an unknown knob
+ * or value.  pw_get_tuning stores the thread's current value in *value.
+ * pw_set_kernel sets PW_TUNE_KERNEL and returns the previous selection (a
+ * PW_KERNEL_* value) or PW_ERR_ARG; pw_get_kernel returns the selection.
+ */
+int pw_set_tuning(int knob, int value);
+int pw_get_tuning(int knob, int *value);
 int pw_set_kernel(int kernel);
 int pw_get_kernel(void);
 

@@ -60,5 +60,76 @@ def build_library(verbose=False, jobs=8):
     return LIB
 
 
+def resource_usage(src="pw_march.hip"):
+    """Compile one source for the device only with the compiler's
+    kernel-resource-usage remarks and return one row per kernel:
+    (template arguments, VGPRs, AGPRs, SGPRs, VGPR spill, scratch bytes per
+    lane, LDS bytes per workgroup, waves per SIMD)."""
+    import re
+    cmd = [HIPCC] + CFLAGS + ["--offload-device-only", "-c", os.path.join(CSRC, src), "-o", os.devnull,
+                              "-Rpass-analysis=kernel-resource-usage"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr)
+    rows, cur = [], None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = {"name": m.group(1)}
+            rows.append(cur)
+            continue
+        m = re.search(r"remark:\s+([A-Za-z /\[\]]+?): (\S+) \[", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = m.group(2)
+    return rows
+
+
+def _march_args(mangled):
+    """Template arguments of a march_kernel symbol, readably."""
+    import re
+    m = re.search(r"march_kernelI(.*?)EEvNS_9MarchArgs", mangled)
+    if not m:
+        return None
+    a = m.group(1)
+    types = {"d": "double", "f": "float", "DF16_": "_Float16", "N12_GLOBAL__N_16bf16_tE": "bf16"}
+    out = []
+    while a:
+        for k in sorted(types, key=len, reverse=True):
+            if a.startswith(k):
+                out.append(types[k])
+                a = a[len(k):]
+                break
+        else:
+            m2 = re.match(r"L([ib])(\d+)E", a)
+            if not m2:
+                out.append(a)
+                break
+            v = m2.group(2)
+            out.append(("true" if v == "1" else "false") if m2.group(1) == "b" else v)
+            a = a[m2.end():]
+    return out
+
+
+def march_resource_table():
+    """Markdown table of the x-marching kernels' compile-time resources."""
+    lines = ["| T | C | NF | WS | WG | TY | D | EH | UPD | VGPRs | SGPRs | VGPR spill | SGPR spill | "
+             "scratch B/lane | LDS B/WG | waves/SIMD |",
+             "|" + "---|" * 16]
+    for r in resource_usage("pw_march.hip"):
+        a = _march_args(r["name"])
+        if not a:
+            continue
+        lines.append("| " + " | ".join(a + [r.get("VGPRs", "?"), r.get("TotalSGPRs", "?"),
+                                           r.get("VGPRs Spill", "?"), r.get("SGPRs Spill", "?"),
+                                           r.get("ScratchSize [bytes/lane]", "?"),
+                                           r.get("LDS Size [bytes/block]", "?"),
+                                           r.get("Occupancy [waves/SIMD]", "?")]) + " |")
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
-    print(build_library(verbose=True))
+    import sys as _sys
+    if len(_sys.argv) > 1 and _sys.argv[1] == "--resource-usage":
+        print(march_resource_table())
+    else:
+        print(build_library(verbose=True))

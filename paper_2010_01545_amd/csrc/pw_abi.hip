@@ -1,12 +1,10 @@
 // pw_abi.hip -- the extern "C" entry points of libpwadvect: argument
 // validation (all of it before any work is queued), kernel selection and
 // launch-error reporting.  See include/pwadvect.h for the contract.
-#include <atomic>
 #include <climits>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 
 #include "../../include/pwadvect.h"
@@ -16,7 +14,18 @@
 namespace {
 
 thread_local char g_err[512] = "";
-std::atomic<int> g_kernel{PW_KERNEL_AUTO};
+
+// Tuning state of the calling thread (pw_set_tuning): read by the calls that
+// thread makes, so threads never see each other's settings.
+struct Tuning {
+    int kernel = PW_KERNEL_AUTO;
+    int variant = -1;                 // < 0: default variant
+    int lx = 0;                       // 0: segment length from the grid
+    int copy_out = PW_COPY_OUT_RUNTIME;
+};
+thread_local Tuning g_tune;
+
+MarchTune march_tune() { return MarchTune{g_tune.variant, g_tune.lx}; }
 
 int fail(int code, const char* fmt, ...)
 {
@@ -190,7 +199,7 @@ int launched(const char* what)
 template <typename T>
 int resolve_kernel(const Geom& g, const Arr* arrs, int n)
 {
-    const int sel = g_kernel.load();
+    const int sel = g_tune.kernel;
     if (sel == PW_KERNEL_DIRECT) return PW_KERNEL_DIRECT;
     bool march = march_supported<T>(g);
     for (int q = 0; q < n && march; q++)
@@ -243,14 +252,16 @@ int do_fwd(const void* u, const void* v, const void* w, const double* tzc1, cons
             for (int q = 0; q < 3; q++) fields[nf++] = ba[q];
     }
     const int kern = resolve_kernel<T>(g, fields, nf);
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and 16-byte aligned arrays");
+    if (kern < 0)
+        return fail(PW_ERR_UNSUPPORTED,
+                    "x-marching kernel needs halo <= 32, columns under 1 GiB and 16-byte aligned arrays");
     FwdArgs<T> a{(const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw, upd,
                  {nullptr, nullptr, nullptr}, beta};
     if (base)
         for (int q = 0; q < 3; q++) a.b[q] = (const T*)base[q];
     (void)hipGetLastError();
     if (kern == PW_KERNEL_MARCH)
-        launch_fwd_march<T, C>(a, g, stream);
+        launch_fwd_march<T, C>(a, g, march_tune(), stream);
     else
         launch_fwd_direct<T, C>(a, g, stream);
     return launched(base ? "pw_advect_fwd_update" : "pw_advect_fwd");
@@ -289,12 +300,14 @@ int do_adj(const void* u, const void* v, const void* w, const void* lu, const vo
     for (int q = 0; q < 6; q++) fields[nf++] = in[q];
     for (int q = 0; q < nout; q++) fields[nf++] = out[q];
     const int kern = resolve_kernel<T>(g, fields, nf);
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and 16-byte aligned arrays");
+    if (kern < 0)
+        return fail(PW_ERR_UNSUPPORTED,
+                    "x-marching kernel needs halo <= 32, columns under 1 GiB and 16-byte aligned arrays");
     AdjArgs<T> a{(const T*)u, (const T*)v, (const T*)w, (const T*)lu, (const T*)lv, (const T*)lw,
                  tzc1, tzc2, tcx, tcy, (T*)su, (T*)sv, (T*)sw, (T*)gu, (T*)gv, (T*)gw};
     (void)hipGetLastError();
     if (kern == PW_KERNEL_MARCH)
-        launch_adj_march<T, C>(a, g, stream);
+        launch_adj_march<T, C>(a, g, march_tune(), stream);
     else
         launch_adj_direct<T, C>(a, g, stream);
     return launched(fused ? "pw_advect_fwd_adj" : "pw_advect_adj");
@@ -418,12 +431,12 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
     sg.nx = chunk;
     const Arr ws[1] = {{workspace, need, 16, "workspace"}};
     const int kern = with_types(dtype, [&](auto t, auto) { return resolve_kernel<decltype(t)>(sg, ws, 1); });
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32");
-    // mapped pinned outputs are written by a copy kernel unless
-    // PW_OFFLOAD_COPY_OUT=runtime asks for the runtime's copies
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and columns under 1 GiB");
+    // outputs go back through the runtime's copies unless the thread asked
+    // for the copy kernel and they are pinned host memory mapped into the
+    // device's address space
     void* od[3] = {nullptr, nullptr, nullptr};
-    const char* env = std::getenv("PW_OFFLOAD_COPY_OUT");
-    bool mapped = !(env && std::strcmp(env, "runtime") == 0);
+    bool mapped = g_tune.copy_out == PW_COPY_OUT_KERNEL;
     for (int f = 0; f < 3 && mapped; ++f) mapped = (od[f] = mapped_host(out[f].p, bytes)) != nullptr;
     const char* what = "";
     const bool march = kern == PW_KERNEL_MARCH;
@@ -432,7 +445,7 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
         T* const o[3] = {(T*)od[0], (T*)od[1], (T*)od[2]};
         return offload_fwd<T, decltype(c)>((const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, g, (T*)su,
                                            (T*)sv, (T*)sw, mapped ? o : nullptr, chunk, workspace, march,
-                                           (hipStream_t)stream, &what);
+                                           march_tune(), (hipStream_t)stream, &what);
     });
     if (e) return fail(PW_ERR_HIP, "pw_advect_fwd_host: %s: %s", what, hipGetErrorString((hipError_t)e));
     return launched("pw_advect_fwd_host");
@@ -497,17 +510,87 @@ int pw_fill_uniform(void* storage, int nx, int ny, int nz, int halo, unsigned lo
     return launched("pw_fill_uniform");
 }
 
-int pw_set_kernel(int kernel)
+int pw_stream_copy(const void* const* src, void* const* dst, int narrays, size_t bytes, int blocks, void* stream)
 {
-    if (kernel != PW_KERNEL_AUTO && kernel != PW_KERNEL_DIRECT && kernel != PW_KERNEL_MARCH)
-        return fail(PW_ERR_ARG, "unknown kernel selection %d", kernel);
-    return g_kernel.exchange(kernel);
+    if (!src || !dst) return fail(PW_ERR_ARG, "src and dst must not be NULL");
+    if (narrays < 1 || narrays > 8) return fail(PW_ERR_ARG, "narrays=%d outside 1..8", narrays);
+    if (bytes % 16) return fail(PW_ERR_ARG, "bytes=%zu is not a multiple of 16", bytes);
+    if (blocks < 0) return fail(PW_ERR_ARG, "blocks=%d: need 0 or more", blocks);
+    if (blocks == 0 && (bytes / 16 + 255) / 256 > 0xffffffffULL)
+        return fail(PW_ERR_SIZE, "one pass over %zu bytes needs more than 2^32 workgroups", bytes);
+    static const char* const sn[8] = {"src[0]", "src[1]", "src[2]", "src[3]", "src[4]", "src[5]", "src[6]", "src[7]"};
+    static const char* const dn[8] = {"dst[0]", "dst[1]", "dst[2]", "dst[3]", "dst[4]", "dst[5]", "dst[6]", "dst[7]"};
+    Arr in[8], out[8];
+    for (int q = 0; q < narrays; ++q) {
+        in[q] = Arr{src[q], bytes, 16, sn[q]};
+        out[q] = Arr{dst[q], bytes, 16, dn[q]};
+    }
+    int rc = check_host_side(in, narrays, out, narrays);
+    if (rc) return rc;
+    Arr all[16];
+    for (int q = 0; q < narrays; ++q) {
+        all[q] = in[q];
+        all[narrays + q] = out[q];
+    }
+    rc = check_device(all, 2 * narrays);
+    if (rc) return rc;
+    (void)hipGetLastError();
+    launch_stream_copy(src, dst, narrays, bytes, blocks, (hipStream_t)stream);
+    return launched("pw_stream_copy");
 }
 
-int pw_get_kernel(void) { return g_kernel.load(); }
+int pw_set_tuning(int knob, int value)
+{
+    switch (knob) {
+    case PW_TUNE_KERNEL:
+        if (value != PW_KERNEL_AUTO && value != PW_KERNEL_DIRECT && value != PW_KERNEL_MARCH)
+            return fail(PW_ERR_ARG, "unknown kernel selection %d", value);
+        g_tune.kernel = value;
+        break;
+    case PW_TUNE_MARCH_VARIANT:
+        if (value < -1 || value >= PW_MARCH_VARIANTS)
+            return fail(PW_ERR_ARG, "march variant %d outside -1..%d", value, PW_MARCH_VARIANTS - 1);
+        g_tune.variant = value;
+        break;
+    case PW_TUNE_MARCH_LX:
+        if (value < 0) return fail(PW_ERR_ARG, "segment length %d: need 0 (automatic) or more", value);
+        g_tune.lx = value;
+        break;
+    case PW_TUNE_COPY_OUT:
+        if (value != PW_COPY_OUT_RUNTIME && value != PW_COPY_OUT_KERNEL)
+            return fail(PW_ERR_ARG, "unknown copy-out mode %d", value);
+        g_tune.copy_out = value;
+        break;
+    default:
+        return fail(PW_ERR_ARG, "unknown tuning knob %d", knob);
+    }
+    return ok();
+}
+
+int pw_get_tuning(int knob, int* value)
+{
+    if (!value) return fail(PW_ERR_ARG, "value is NULL");
+    switch (knob) {
+    case PW_TUNE_KERNEL: *value = g_tune.kernel; break;
+    case PW_TUNE_MARCH_VARIANT: *value = g_tune.variant; break;
+    case PW_TUNE_MARCH_LX: *value = g_tune.lx; break;
+    case PW_TUNE_COPY_OUT: *value = g_tune.copy_out; break;
+    default: return fail(PW_ERR_ARG, "unknown tuning knob %d", knob);
+    }
+    return ok();
+}
+
+int pw_set_kernel(int kernel)
+{
+    const int prev = g_tune.kernel;
+    const int rc = pw_set_tuning(PW_TUNE_KERNEL, kernel);
+    return rc ? rc : prev;
+}
+
+int pw_get_kernel(void) { return g_tune.kernel; }
 
 const char* pw_last_error(void) { return g_err; }
 
-int pw_version(void) { return 100; }
+int pw_version(void) { return 200; }
 
 }  // extern "C"

@@ -42,10 +42,19 @@ struct AdjArgs {
 template <typename T, typename C> void launch_fwd_direct(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
 template <typename T, typename C> void launch_adj_direct(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
 
-// x-marching kernels (any nz >= 2, halo <= 32, 16-byte aligned arrays).
+// x-marching kernels (any nz >= 2, halo <= 32, 16-byte aligned arrays,
+// columns shorter than 1 GiB).  MarchTune carries the calling thread's
+// choice of variant (< 0: the default for the type pair and output set) and
+// segment length in planes (0: chosen from the grid).
+struct MarchTune {
+    int variant;
+    int lx;
+};
 template <typename T> bool march_supported(const Geom& g);
-template <typename T, typename C> void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s);
-template <typename T, typename C> void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s);
+template <typename T, typename C>
+void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, MarchTune t, hipStream_t s);
+template <typename T, typename C>
+void launch_adj_march(const AdjArgs<T>& a, const Geom& g, MarchTune t, hipStream_t s);
 
 // Utilities.
 template <typename T> void launch_halo_periodic(T* st, const Geom& g, hipStream_t s);
@@ -54,11 +63,15 @@ template <typename T> void launch_fill_uniform(T* st, const Geom& g, unsigned lo
                                                int field_id, double amp, int zero_lids,
                                                hipStream_t s);
 
+// Plain streaming copy of n arrays (pw_copyref.hip), the bandwidth reference.
+void launch_stream_copy(const void* const* src, void* const* dst, int n, size_t bytes, int blocks, hipStream_t s);
+
 // Host-resident fields: chunked, pipelined forward (pw_offload.hip).  out_dev
 // holds the device addresses of su, sv, sw when they are mapped pinned host
-// memory (a copy kernel then writes them), else nullptr (runtime copies).
+// memory and the copy kernel was asked for (it then writes them), else
+// nullptr (runtime copies).
 size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es);
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
                 const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
-                hipStream_t stream, const char** what);
+                MarchTune tune, hipStream_t stream, const char** what);

@@ -41,7 +41,6 @@
 // 8 XCDs; ids are remapped so that each XCD receives a contiguous range of
 // strips, so the halo columns shared by neighbouring strips are read through
 // the same L2.
-#include <cstdlib>
 #include <type_traits>
 
 #include "pw_half.h"
@@ -496,18 +495,24 @@ struct Launch {
     int LX, nstrips, nchunk, nblocks, grid;
 };
 
-Launch plan(const Geom& g, int TY)
+// Segment length: the caller's choice (lx > 0), else segments of up to 128
+// planes (measured best at 4096 x 4096 x 64), shorter ones on smaller grids
+// so that at least kTargetBlocks workgroups exist (about 32 per compute unit)
+// and the last round of workgroups is a small part of the launch.  A segment
+// reads its two end planes once more than the interior ones, so segments are
+// kept at kMinLX planes or more.
+constexpr int kTargetBlocks = 8192;
+constexpr int kMinLX = 4;
+constexpr int kMaxLX = 128;
+
+Launch plan(const Geom& g, int TY, int lx)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
     l.nchunk = g.nz <= NZ ? 1 : (g.nz + kChunk - 1) / kChunk;
-    int lx = 0;
-    if (const char* e = std::getenv("PW_MARCH_LX")) lx = std::atoi(e);
     if (lx <= 0) {
-        // Segments of up to 128 planes (measured best at 4096 x 4096 x 64);
-        // shorter ones on small grids so that about 8192 workgroups exist.
-        const long long want = ((long long)g.nx * l.nstrips * l.nchunk + 8191) / 8192;
-        lx = want < 16 ? 16 : (want > 128 ? 128 : (int)want);
+        const long long want = ((long long)g.nx * l.nstrips * l.nchunk + kTargetBlocks - 1) / kTargetBlocks;
+        lx = want < kMinLX ? kMinLX : (want > kMaxLX ? kMaxLX : (int)want);
     }
     l.LX = lx;
     const int nseg = (g.nx + lx - 1) / lx;
@@ -532,17 +537,22 @@ constexpr int lds_bytes()
     return (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
 }
 
+// The LDS ring is static shared memory (no dynamic LDS is ever requested),
+// so the compiler sizes each instantiation's group segment; the caps keep it
+// within the 160 KiB of a compute unit.
+static_assert(kLdsCap[0] <= 163840 && kLdsCap[4] <= 163840 && kLdsCap[6] <= 163840, "LDS of one compute unit");
+
 template <typename T, typename C, int NF, bool WS, bool WG, int V, int UPD>
-void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
+void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, hipStream_t s)
 {
     constexpr int TY = kTY[V], D = kD[V];
     constexpr bool EH = kEH[V];
     if constexpr (lds_bytes<T, C, NF, TY>() <= kLdsCap[V]) {
-        const Launch l = plan(g, TY);
+        const Launch l = plan(g, TY, lx);
         hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, EH, UPD>), dim3(l.grid),
                            dim3(64 * (EH ? TY : TY + 2)), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
     } else {
-        go<T, C, NF, WS, WG, 0, UPD>(m, g, s);
+        go<T, C, NF, WS, WG, 0, UPD>(m, g, lx, s);
     }
 }
 
@@ -558,8 +568,8 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
 //   * 16-bit storage: the adjoint and the accumulating update in 8-column
 //     strips with edge waves (8-10% faster), the bfloat16 fused pass in
 //     16-column strips with edge waves (5%).
-// Deeper prefetch (D = 4) measured no faster.  PW_MARCH_VARIANT=0..6
-// overrides the choice for sweeps.
+// Deeper prefetch (D = 4) measured no faster.  A thread's tuning state
+// (pw_set_tuning) can name another variant, for sweeps.
 template <typename T, typename C, int NF, bool WS, int UPD>
 int default_variant()
 {
@@ -576,34 +586,33 @@ int default_variant()
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
-void dispatch(const MarchArgs<T, NF>& m, const Geom& g, hipStream_t s)
+void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t s)
 {
-    int v = default_variant<T, C, NF, WS, UPD>();
-    if (const char* e = std::getenv("PW_MARCH_VARIANT")) {
-        const int q = std::atoi(e);
-        if (q >= 0 && q < kVariants) v = q;
-    }
+    const int v = (t.variant >= 0 && t.variant < kVariants) ? t.variant : default_variant<T, C, NF, WS, UPD>();
     switch (v) {
-    case 1: go<T, C, NF, WS, WG, 1, UPD>(m, g, s); break;
-    case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, s); break;
-    case 3: go<T, C, NF, WS, WG, 3, UPD>(m, g, s); break;
-    case 4: go<T, C, NF, WS, WG, 4, UPD>(m, g, s); break;
-    case 5: go<T, C, NF, WS, WG, 5, UPD>(m, g, s); break;
-    case 6: go<T, C, NF, WS, WG, 6, UPD>(m, g, s); break;
-    default: go<T, C, NF, WS, WG, 0, UPD>(m, g, s); break;
+    case 1: go<T, C, NF, WS, WG, 1, UPD>(m, g, t.lx, s); break;
+    case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, t.lx, s); break;
+    case 3: go<T, C, NF, WS, WG, 3, UPD>(m, g, t.lx, s); break;
+    case 4: go<T, C, NF, WS, WG, 4, UPD>(m, g, t.lx, s); break;
+    case 5: go<T, C, NF, WS, WG, 5, UPD>(m, g, t.lx, s); break;
+    case 6: go<T, C, NF, WS, WG, 6, UPD>(m, g, t.lx, s); break;
+    default: go<T, C, NF, WS, WG, 0, UPD>(m, g, t.lx, s); break;
     }
 }
 
 }  // namespace
 
+// The buffer descriptors address one column with 32-bit byte offsets, and a
+// lane that must not store gets the offset kOutOfRange: a column must be
+// shorter than that for such stores to fall outside it.
 template <typename T>
 bool march_supported(const Geom& g)
 {
-    return g.nz >= 2 && g.h <= 32;
+    return g.nz >= 2 && g.h <= 32 && (long long)g.Sz * (long long)sizeof(T) < (long long)kOutOfRange;
 }
 
 template <typename T, typename C>
-void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
+void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, MarchTune t, hipStream_t s)
 {
     MarchArgs<T, 3> m;
     m.in[0] = a.u;
@@ -620,15 +629,15 @@ void launch_fwd_march(const FwdArgs<T>& a, const Geom& g, hipStream_t s)
     m.tcy = a.tcy;
     m.beta = a.beta;
     if (a.upd == 1)
-        dispatch<T, C, 3, true, false, 1>(m, g, s);
+        dispatch<T, C, 3, true, false, 1>(m, g, t, s);
     else if (a.upd == 2)
-        dispatch<T, C, 3, true, false, 2>(m, g, s);
+        dispatch<T, C, 3, true, false, 2>(m, g, t, s);
     else
-        dispatch<T, C, 3, true, false, 0>(m, g, s);
+        dispatch<T, C, 3, true, false, 0>(m, g, t, s);
 }
 
 template <typename T, typename C>
-void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
+void launch_adj_march(const AdjArgs<T>& a, const Geom& g, MarchTune t, hipStream_t s)
 {
     MarchArgs<T, 6> m;
     m.in[0] = a.u;
@@ -650,22 +659,22 @@ void launch_adj_march(const AdjArgs<T>& a, const Geom& g, hipStream_t s)
     m.tcy = a.tcy;
     m.beta = 0.0;
     if (a.su)
-        dispatch<T, C, 6, true, true>(m, g, s);
+        dispatch<T, C, 6, true, true>(m, g, t, s);
     else
-        dispatch<T, C, 6, false, true>(m, g, s);
+        dispatch<T, C, 6, false, true>(m, g, t, s);
 }
 
 template bool march_supported<double>(const Geom&);
 template bool march_supported<float>(const Geom&);
 template bool march_supported<_Float16>(const Geom&);
 template bool march_supported<bf16_t>(const Geom&);
-template void launch_fwd_march<_Float16, float>(const FwdArgs<_Float16>&, const Geom&, hipStream_t);
-template void launch_fwd_march<bf16_t, float>(const FwdArgs<bf16_t>&, const Geom&, hipStream_t);
-template void launch_adj_march<_Float16, float>(const AdjArgs<_Float16>&, const Geom&, hipStream_t);
-template void launch_adj_march<bf16_t, float>(const AdjArgs<bf16_t>&, const Geom&, hipStream_t);
-template void launch_fwd_march<double, double>(const FwdArgs<double>&, const Geom&, hipStream_t);
-template void launch_fwd_march<float, float>(const FwdArgs<float>&, const Geom&, hipStream_t);
-template void launch_fwd_march<float, double>(const FwdArgs<float>&, const Geom&, hipStream_t);
-template void launch_adj_march<double, double>(const AdjArgs<double>&, const Geom&, hipStream_t);
-template void launch_adj_march<float, float>(const AdjArgs<float>&, const Geom&, hipStream_t);
-template void launch_adj_march<float, double>(const AdjArgs<float>&, const Geom&, hipStream_t);
+template void launch_fwd_march<_Float16, float>(const FwdArgs<_Float16>&, const Geom&, MarchTune, hipStream_t);
+template void launch_fwd_march<bf16_t, float>(const FwdArgs<bf16_t>&, const Geom&, MarchTune, hipStream_t);
+template void launch_adj_march<_Float16, float>(const AdjArgs<_Float16>&, const Geom&, MarchTune, hipStream_t);
+template void launch_adj_march<bf16_t, float>(const AdjArgs<bf16_t>&, const Geom&, MarchTune, hipStream_t);
+template void launch_fwd_march<double, double>(const FwdArgs<double>&, const Geom&, MarchTune, hipStream_t);
+template void launch_fwd_march<float, float>(const FwdArgs<float>&, const Geom&, MarchTune, hipStream_t);
+template void launch_fwd_march<float, double>(const FwdArgs<float>&, const Geom&, MarchTune, hipStream_t);
+template void launch_adj_march<double, double>(const AdjArgs<double>&, const Geom&, MarchTune, hipStream_t);
+template void launch_adj_march<float, float>(const AdjArgs<float>&, const Geom&, MarchTune, hipStream_t);
+template void launch_adj_march<float, double>(const AdjArgs<float>&, const Geom&, MarchTune, hipStream_t);

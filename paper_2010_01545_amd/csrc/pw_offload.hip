@@ -19,16 +19,17 @@
 // The internal streams and events are created once per device (default
 // priority) and kept for the life of the process.
 //
-// Copies out.  When the output arrays are pinned host memory mapped into the
-// device's address space (out_dev holds their device addresses), a copy
-// kernel on the copy-out stream writes each slab's rows to them; otherwise
-// (pageable memory) the runtime's 2-D copy does.  The kernel leaves the copy
-// engines to the inputs: with both directions on copy engines the runtime
-// now and then puts them on one engine, and the two transfers serialise
-// (measured at 4096 x 1024 x 64 FP64: 147-151 ms per call, or about 250 ms in
-// roughly one call of five, against 165-171 ms every call with the copy
-// kernel; on another kind of machine 210 ms, or about 457 ms in one call of
-// four, against 260-274 ms).
+// Copies out.  By default the runtime's 2-D copy writes each slab's rows
+// back.  When the caller's thread asks for the copy kernel and the output
+// arrays are pinned host memory mapped into the device's address space
+// (out_dev holds their device addresses), a copy kernel on the copy-out
+// stream writes them instead, leaving the copy engines to the inputs.  With
+// both directions on copy engines the runtime now and then puts them on one
+// engine and the two transfers serialise, but on average the runtime's copies
+// were as fast or faster (measured at 4096 x 1024 x 64 FP64: 147-151 ms per
+// call, or about 250 ms in roughly one call of five, against 165-171 ms every
+// call with the copy kernel; on another kind of machine 211 ms against
+// 260-274 ms).
 #include <mutex>
 
 #include "../../include/pwadvect.h"
@@ -40,8 +41,8 @@ namespace {
 constexpr int kBuffers = 3;
 constexpr int kCopyBlock = 256;
 
-// rows x rowunits units of U (16 or 4 bytes) from src to dst, both with a
-// pitch of pitchunits units; blockIdx.y strides over rows.
+// rows x rowunits units of U from src to dst, both with a pitch of
+// pitchunits units; blockIdx.y strides over rows.
 template <typename U>
 __global__ void __launch_bounds__(kCopyBlock)
 copy_rows_kernel(const U* __restrict__ src, U* __restrict__ dst, size_t pitchunits, size_t rowunits, int rows)
@@ -54,20 +55,37 @@ copy_rows_kernel(const U* __restrict__ src, U* __restrict__ dst, size_t pitchuni
     }
 }
 
-void copy_rows(const void* src, void* dst, size_t pitch, size_t row, int rows, hipStream_t s)
+// Widest access unit (16, 8, 4 or 2 bytes) that divides both addresses, the
+// pitch and the row length, so every row is copied whole: rows of 16-bit
+// elements can be any even number of bytes long.
+size_t copy_unit(const void* src, const void* dst, size_t pitch, size_t row)
 {
-    const bool v16 = ((uintptr_t)src | (uintptr_t)dst | pitch | row) % 16 == 0;
-    const size_t unit = v16 ? 16 : 4;   // element sizes are 4 or 8 bytes
-    const size_t units = row / unit;
+    const uintptr_t all = (uintptr_t)src | (uintptr_t)dst | (uintptr_t)pitch | (uintptr_t)row;
+    for (size_t u = 16; u > 2; u /= 2)
+        if (all % u == 0) return u;
+    return 2;
+}
+
+template <typename U>
+void copy_rows_as(const void* src, void* dst, size_t pitch, size_t row, int rows, hipStream_t s)
+{
+    const size_t units = row / sizeof(U);
     unsigned bx = (unsigned)((units + kCopyBlock - 1) / kCopyBlock);
     if (bx > 1024) bx = 1024;
     const dim3 grid(bx, (unsigned)(rows < 65535 ? rows : 65535));
-    if (v16)
-        hipLaunchKernelGGL(copy_rows_kernel<uint4>, grid, dim3(kCopyBlock), 0, s, (const uint4*)src, (uint4*)dst,
-                           pitch / 16, units, rows);
-    else
-        hipLaunchKernelGGL(copy_rows_kernel<unsigned>, grid, dim3(kCopyBlock), 0, s, (const unsigned*)src,
-                           (unsigned*)dst, pitch / 4, units, rows);
+    hipLaunchKernelGGL(copy_rows_kernel<U>, grid, dim3(kCopyBlock), 0, s, (const U*)src, (U*)dst,
+                       pitch / sizeof(U), units, rows);
+}
+
+// Element sizes are 2, 4 or 8 bytes, so src, dst, pitch and row are even.
+void copy_rows(const void* src, void* dst, size_t pitch, size_t row, int rows, hipStream_t s)
+{
+    switch (copy_unit(src, dst, pitch, row)) {
+    case 16: copy_rows_as<uint4>(src, dst, pitch, row, rows, s); break;
+    case 8: copy_rows_as<unsigned long long>(src, dst, pitch, row, rows, s); break;
+    case 4: copy_rows_as<unsigned>(src, dst, pitch, row, rows, s); break;
+    default: copy_rows_as<unsigned short>(src, dst, pitch, row, rows, s); break;
+    }
 }
 
 struct DeviceQueues {
@@ -123,7 +141,7 @@ size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es)
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
                 const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
-                hipStream_t stream, const char** what)
+                MarchTune tune, hipStream_t stream, const char** what)
 {
     DeviceQueues* q = nullptr;
     hipError_t e = queues_for_current_device(&q);
@@ -177,7 +195,7 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
         FwdArgs<T> a{buf(b, 0), buf(b, 1), buf(b, 2), tzc1, tzc2, tcx, tcy, buf(b, 3), buf(b, 4), buf(b, 5)};
         (void)hipGetLastError();
         if (use_march)
-            launch_fwd_march<T, C>(a, sg, stream);
+            launch_fwd_march<T, C>(a, sg, tune, stream);
         else
             launch_fwd_direct<T, C>(a, sg, stream);
         if ((e = hipGetLastError()) != hipSuccess) { *what = "kernel launch"; return (int)e; }
@@ -203,18 +221,12 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
     return 0;
 }
 
-template int offload_fwd<double, double>(const double*, const double*, const double*, const double*, const double*,
-                                         double, double, const Geom&, double*, double*, double*, double* const*, int,
-                                         void*, bool, hipStream_t, const char**);
-template int offload_fwd<float, float>(const float*, const float*, const float*, const double*, const double*, double,
-                                       double, const Geom&, float*, float*, float*, float* const*, int, void*, bool,
-                                       hipStream_t, const char**);
-template int offload_fwd<float, double>(const float*, const float*, const float*, const double*, const double*,
-                                        double, double, const Geom&, float*, float*, float*, float* const*, int,
-                                        void*, bool, hipStream_t, const char**);
-template int offload_fwd<_Float16, float>(const _Float16*, const _Float16*, const _Float16*, const double*,
-                                          const double*, double, double, const Geom&, _Float16*, _Float16*,
-                                          _Float16*, _Float16* const*, int, void*, bool, hipStream_t, const char**);
-template int offload_fwd<bf16_t, float>(const bf16_t*, const bf16_t*, const bf16_t*, const double*, const double*,
-                                        double, double, const Geom&, bf16_t*, bf16_t*, bf16_t*, bf16_t* const*, int,
-                                        void*, bool, hipStream_t, const char**);
+#define PW_OFFLOAD_INSTANCE(T, C)                                                                            \
+    template int offload_fwd<T, C>(const T*, const T*, const T*, const double*, const double*, double, double, \
+                                   const Geom&, T*, T*, T*, T* const*, int, void*, bool, MarchTune, hipStream_t, \
+                                   const char**);
+PW_OFFLOAD_INSTANCE(double, double)
+PW_OFFLOAD_INSTANCE(float, float)
+PW_OFFLOAD_INSTANCE(float, double)
+PW_OFFLOAD_INSTANCE(_Float16, float)
+PW_OFFLOAD_INSTANCE(bf16_t, float)

@@ -21,6 +21,10 @@ LIB_PATH = os.path.join(HERE, "libpwadvect.so")
 
 PW_F64, PW_F32, PW_F32_F64, PW_F16, PW_BF16 = 0, 1, 2, 3, 4
 KERNELS = {"auto": 0, "direct": 1, "march": 2}
+# tuning knobs of the calling thread (pw_set_tuning)
+TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT = 0, 1, 2, 3
+MARCH_VARIANTS = 7
+COPY_OUT = {"runtime": 0, "kernel": 1}
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
           -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
 
@@ -45,9 +49,13 @@ lib.pw_advect_fwd_host.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + 
 lib.pw_offload_workspace_bytes.argtypes = [_i] * 6
 lib.pw_offload_workspace_bytes.restype = ctypes.c_size_t
 lib.pw_set_kernel.argtypes = [_i]
+lib.pw_set_tuning.argtypes = [_i, _i]
+lib.pw_get_tuning.argtypes = [_i, ctypes.POINTER(_i)]
+lib.pw_stream_copy.argtypes = [_vp, _vp, _i, ctypes.c_size_t, _i, _vp]
 lib.pw_last_error.restype = ctypes.c_char_p
-for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_advect_fwd_update", "pw_halo_periodic",
-           "pw_pad_periodic", "pw_fill_uniform", "pw_set_kernel", "pw_get_kernel", "pw_version"):
+for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_advect_fwd_update",
+           "pw_halo_periodic", "pw_pad_periodic", "pw_fill_uniform", "pw_stream_copy", "pw_set_kernel",
+           "pw_get_kernel", "pw_set_tuning", "pw_get_tuning", "pw_version"):
     getattr(lib, _f).restype = ctypes.c_int
 
 
@@ -226,8 +234,71 @@ def fill_uniform(storage, halo, seed, field_id, amp=10.0, zero_lids=False):
     return storage
 
 
+def stream_copy(src, dst, blocks=0):
+    """One launch of the library's plain streaming copy: dst[q] <- src[q] for
+    lists of equally sized contiguous device tensors (the bandwidth reference
+    of the advection kernels).  ``blocks`` = 0: one 16-byte unit per thread
+    and array; > 0: that many workgroups striding over the arrays."""
+    if len(src) != len(dst) or not 1 <= len(src) <= 8:
+        raise ValueError("1..8 source and destination tensors")
+    nbytes = src[0].numel() * src[0].element_size()
+    for t in list(src) + list(dst):
+        if not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() != nbytes:
+            raise ValueError("stream_copy takes contiguous device tensors of one byte size")
+    n = len(src)
+    sp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in src])
+    dp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in dst])
+    _check(lib.pw_stream_copy(ctypes.cast(sp, _vp), ctypes.cast(dp, _vp), n, nbytes, int(blocks), _stream()))
+
+
+def get_tuning(knob):
+    """Current value of tuning knob ``knob`` (TUNE_*) of the calling thread."""
+    v = _i(0)
+    _check(lib.pw_get_tuning(int(knob), ctypes.byref(v)))
+    return v.value
+
+
+def set_tuning(knob, value):
+    """Set tuning knob ``knob`` (TUNE_*) of the calling thread; returns the
+    previous value.  No knob changes a result."""
+    prev = get_tuning(knob)
+    _check(lib.pw_set_tuning(int(knob), int(value)))
+    return prev
+
+
+class tuning:
+    """Context manager: set tuning knobs of the calling thread for a block
+    and restore them afterwards, e.g. ``with pw.tuning(variant=3, lx=7):``.
+    Keywords: kernel ('auto', 'direct', 'march'), variant (-1..6), lx (planes
+    per marching workgroup, 0 = automatic), copy_out ('runtime', 'kernel')."""
+
+    def __init__(self, kernel=None, variant=None, lx=None, copy_out=None):
+        self.want = []
+        if kernel is not None:
+            self.want.append((TUNE_KERNEL, KERNELS[kernel]))
+        if variant is not None:
+            self.want.append((TUNE_MARCH_VARIANT, int(variant)))
+        if lx is not None:
+            self.want.append((TUNE_MARCH_LX, int(lx)))
+        if copy_out is not None:
+            self.want.append((TUNE_COPY_OUT, COPY_OUT[copy_out]))
+        self.saved = []
+
+    def __enter__(self):
+        for knob, value in self.want:
+            self.saved.append((knob, set_tuning(knob, value)))
+        return self
+
+    def __exit__(self, *exc):
+        for knob, value in reversed(self.saved):
+            set_tuning(knob, value)
+        self.saved = []
+        return False
+
+
 def set_kernel(name):
-    """Select 'auto', 'direct' or 'march'; returns the previous selection."""
+    """Select 'auto', 'direct' or 'march' for the calling thread; returns the
+    previous selection."""
     prev = lib.pw_set_kernel(KERNELS[name])
     _check(min(prev, 0))
     return {v: k for k, v in KERNELS.items()}[prev]

@@ -13,8 +13,8 @@ import oracle
 from paper_2010_01545_amd import inputs
 
 H = inputs.HALO
-# every x-marching variant the library builds (PW_MARCH_VARIANT values)
-MARCH_VARIANTS = [str(v) for v in range(7)]
+# every x-marching variant the library builds (PW_TUNE_MARCH_VARIANT values)
+MARCH_VARIANTS = list(range(7))
 
 
 def log(msg):

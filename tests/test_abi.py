@@ -182,3 +182,88 @@ def test_utility_checks(lib):
     prev = lib.pw_set_kernel(1)
     assert lib.pw_get_kernel() == 1
     lib.pw_set_kernel(prev)
+
+
+# ---------------------------------------------------------------- tuning knobs
+PW_TUNE_KERNEL, PW_TUNE_MARCH_VARIANT, PW_TUNE_MARCH_LX, PW_TUNE_COPY_OUT = 0, 1, 2, 3
+
+
+def _get(lib, knob):
+    v = ctypes.c_int(-99)
+    rc = lib.pw_get_tuning(knob, ctypes.byref(v))
+    return rc, v.value
+
+
+def test_tuning_knobs_set_get_and_reject(lib):
+    lib.pw_get_tuning.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    defaults = {PW_TUNE_KERNEL: 0, PW_TUNE_MARCH_VARIANT: -1, PW_TUNE_MARCH_LX: 0, PW_TUNE_COPY_OUT: 0}
+    for knob, d in defaults.items():
+        assert _get(lib, knob) == (PW_OK, d)
+    for knob, good, bad in ((PW_TUNE_KERNEL, 2, 3), (PW_TUNE_MARCH_VARIANT, 6, 7),
+                            (PW_TUNE_MARCH_LX, 9, -1), (PW_TUNE_COPY_OUT, 1, 2)):
+        assert lib.pw_set_tuning(knob, good) == PW_OK
+        assert _get(lib, knob) == (PW_OK, good)
+        assert lib.pw_set_tuning(knob, bad) == PW_ERR_ARG
+        assert _get(lib, knob) == (PW_OK, good)          # unchanged by a refused value
+        assert lib.pw_set_tuning(knob, defaults[knob]) == PW_OK
+    assert lib.pw_set_tuning(PW_TUNE_MARCH_VARIANT, -2) == PW_ERR_ARG
+    assert lib.pw_set_tuning(17, 0) == PW_ERR_ARG
+    assert _get(lib, 17)[0] == PW_ERR_ARG
+    assert lib.pw_get_tuning(PW_TUNE_KERNEL, None) == PW_ERR_ARG
+    # pw_set_kernel returns the previous family
+    assert lib.pw_set_kernel(1) == 0 and lib.pw_get_kernel() == 1
+    assert lib.pw_set_kernel(5) == PW_ERR_ARG and lib.pw_get_kernel() == 1
+    assert lib.pw_set_kernel(0) == 1
+
+
+def test_tuning_is_per_thread(lib):
+    """A knob set on one thread is invisible to another (the library keeps no
+    process-wide selection)."""
+    import threading
+    lib.pw_get_tuning.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    seen = {}
+
+    def worker():
+        seen["before"] = _get(lib, PW_TUNE_MARCH_VARIANT)
+        lib.pw_set_tuning(PW_TUNE_MARCH_VARIANT, 4)
+        lib.pw_set_kernel(2)
+        seen["after"] = _get(lib, PW_TUNE_MARCH_VARIANT)
+    assert lib.pw_set_tuning(PW_TUNE_MARCH_VARIANT, 3) == PW_OK
+    t = threading.Thread(target=worker)
+    t.start()
+    t.join()
+    assert seen == {"before": (PW_OK, -1), "after": (PW_OK, 4)}
+    assert _get(lib, PW_TUNE_MARCH_VARIANT) == (PW_OK, 3)
+    assert lib.pw_get_kernel() == 0
+    lib.pw_set_tuning(PW_TUNE_MARCH_VARIANT, -1)
+
+
+def test_library_reads_no_environment():
+    """No getenv in the library's imports: kernel choice and every other
+    setting come from the caller's arguments and tuning calls only."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--undefined-only", LIB], capture_output=True, text=True, check=True).stdout
+    names = {line.split()[-1].split("@")[0] for line in out.splitlines() if line.strip()}
+    assert not {"getenv", "secure_getenv"} & names
+
+
+# ---------------------------------------------------------------- streaming copy reference
+def test_stream_copy_checks(lib):
+    vp = ctypes.c_void_p
+    lib.pw_stream_copy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, vp]
+
+    def call(src, dst, n, nbytes, blocks=0):
+        s = (vp * len(src))(*src)
+        d = (vp * len(dst))(*dst)
+        return lib.pw_stream_copy(ctypes.cast(s, vp), ctypes.cast(d, vp), n, nbytes, blocks, None)
+
+    src, dst = ADDR[:3], ADDR[3:6]
+    assert lib.pw_stream_copy(None, None, 3, 4096, 0, None) == PW_ERR_ARG
+    assert call(src, dst, 0, 4096) == PW_ERR_ARG
+    assert call(ADDR[:9], ADDR[:9], 9, 4096) == PW_ERR_ARG
+    assert call(src, dst, 3, 4100) == PW_ERR_ARG                       # not a multiple of 16
+    assert call(src, dst, 3, 4096, -1) == PW_ERR_ARG
+    assert call([ADDR[0] + 8] + src[1:], dst, 3, 4096) == PW_ERR_ALIGN
+    assert call(src, [dst[0], dst[1], src[2] + 16], 3, 4096) == PW_ERR_ALIAS   # dst overlaps a source
+    assert call(src, [dst[0], dst[0] + 4080, dst[2]], 3, 4096) == PW_ERR_ALIAS  # two destinations overlap
+    assert call([0] + src[1:], dst, 3, 4096) == PW_ERR_ARG             # NULL entry

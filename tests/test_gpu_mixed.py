@@ -12,8 +12,6 @@ float inputs (widened):
   * the fused launch, the separate launches, both kernel families and every
     marching variant give identical bits.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -119,41 +117,13 @@ def test_every_march_variant_matches_direct(pw, variant):
     st, sl = dev_f32(pw, as_f32(fields)), dev_f32(pw, as_f32(lams))
     args = coef_dev(coef) + (coef[2], coef[3], H)
     ref = with_kernel(pw, "direct", lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
-    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
-    os.environ["PW_MARCH_VARIANT"] = variant
-    os.environ["PW_MARCH_LX"] = "7"
-    try:
+    with pw.tuning(variant=variant, lx=7):
         got = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
         got_g = with_kernel(pw, "march", lambda: pw.adj(*st, *sl, *args, compute=F64))
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
     for a, b in zip(ref, got):
         assert np.array_equal(interior(a), interior(b))
     for a, b in zip(ref[3:], got_g):
         assert np.array_equal(interior(a), interior(b))
-
-
-def test_offload_mixed_matches_device_path(pw):
-    fields, _, coef = host_case(20, 13, 64, 51)
-    f32 = as_f32(fields)
-    st = dev_f32(pw, f32)
-    ref = [o.cpu().numpy() for o in pw.fwd(*st, *coef_dev(coef), coef[2], coef[3], H, compute=F64)]
-    host = []
-    for t in st:
-        h = torch.empty(t.shape, dtype=torch.float32, pin_memory=True)
-        h.copy_(t)
-        host.append(h)
-    outs = [torch.full(host[0].shape, float("nan"), dtype=torch.float32, pin_memory=True) for _ in range(3)]
-    ws = torch.empty(pw.offload_workspace_bytes(host[0].shape, H, torch.float32, 6, compute=F64),
-                     dtype=torch.uint8, device=DEV)
-    pw.fwd_host(*host, *coef_dev(coef), coef[2], coef[3], H, *outs, 6, ws, compute=F64)
-    torch.cuda.current_stream().synchronize()
-    for g, r in zip(outs, ref):
-        assert np.array_equal(g.numpy()[H:-H, H:-H], r[H:-H, H:-H])
 
 
 def test_mixed_rejects_double_storage(pw):

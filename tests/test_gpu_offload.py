@@ -1,18 +1,43 @@
-"""GPU tests of the host-resident offload path (pw_advect_fwd_host): the
-pipelined slab transfer must reproduce the device-resident forward bit for
-bit, write only interior columns of the host outputs, and order itself on the
-caller's stream."""
-import os
+"""GPU tests of the host-resident offload path (pw_advect_fwd_host), against
+the oracle.
 
+For every storage type the offload of host arrays must match the FP64 oracle
+on the same (storage-rounded) inputs with the bar of the device path for that
+type (bitwise for FP64; bitwise to the oracle rounded to float for FP32
+storage with FP64 arithmetic; the FP32 and 16-bit error bounds otherwise, see
+test_gpu_parity and test_gpu_half), give the device path's bits, write only
+interior columns of the host outputs, and order itself on the caller's
+stream.  Shapes include odd ny and odd nz with halo 1 and 2, whose 16-bit
+output rows are not a multiple of 4 bytes long, for each way the outputs come
+back: pinned memory through the runtime's copies (the default) or through the
+library's copy kernel, and pageable memory.
+"""
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from _helpers import H, host_case, log
+from paper_2010_01545_amd import inputs
+from _helpers import host_case, log
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
+
+# storage dtype, arithmetic dtype (None: the storage dtype), inputs.round_storage kind
+KINDS = {
+    "f64": (torch.float64, None, "f64"),
+    "f32": (torch.float32, None, "f32"),
+    "f32f64": (torch.float32, torch.float64, "f32"),
+    "f16": (torch.float16, None, "f16"),
+    "bf16": (torch.bfloat16, None, "bf16"),
+}
+# (nx, ny, nz, halo, seed), chunk sizes
+SHAPES = [((20, 13, 64, 2, 31), (1, 3, 7, 20)),
+          ((9, 7, 7, 2, 32), (4, 9)),
+          ((5, 7, 3, 2, 35), (2, 5)),
+          ((9, 7, 3, 1, 36), (2, 4)),
+          ((6, 5, 3, 1, 34), (5,))]
+MODES = ["pinned_runtime_copy", "pinned_copy_kernel", "pageable"]
 
 
 @pytest.fixture(scope="module")
@@ -24,109 +49,109 @@ def pw():
 
 def _host(arr, dtype, pinned):
     t = torch.empty(arr.shape, dtype=dtype, pin_memory=pinned)
-    t.copy_(torch.from_numpy(arr))
+    t.copy_(torch.from_numpy(arr))      # exact: arr already holds storage-type values
     return t
 
 
-@pytest.fixture
-def copy_out_env():
-    """Sets PW_OFFLOAD_COPY_OUT for one test (the library reads it per call)."""
-    old = os.environ.get("PW_OFFLOAD_COPY_OUT")
-
-    def set_(runtime):
-        os.environ["PW_OFFLOAD_COPY_OUT"] = "runtime" if runtime else "kernel"
-    yield set_
-    if old is None:
-        os.environ.pop("PW_OFFLOAD_COPY_OUT", None)
-    else:
-        os.environ["PW_OFFLOAD_COPY_OUT"] = old
+def within_bar(kind, got, ref, mag):
+    """The device path's parity bar for storage kind ``kind``: got and ref
+    are interior float64 arrays, mag the oracle's error magnitude T."""
+    if kind == "f64":
+        return np.array_equal(got, ref)
+    if kind == "f32f64":
+        return np.array_equal(got, ref.astype(np.float32).astype(np.float64))
+    u16, sub = {"f32": (0.0, 0.0), "f16": (2.0 ** -11, 2.0 ** -25), "bf16": (2.0 ** -8, 0.0)}[kind]
+    bound = 16 * 2.0 ** -24 * mag + u16 * np.abs(ref) + sub
+    return not np.any(np.abs(got - ref) > bound)
 
 
-# pinned outputs are written back by the library's copy kernel, or by the
-# runtime's copies when asked; pageable outputs always by the runtime
-@pytest.mark.parametrize("mode", ["pinned", "pinned_runtime_copy", "pageable"])
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("shape,chunks", [((20, 13, 64, 31), (1, 3, 7, 20, 64)),
-                                          ((9, 6, 7, 32), (4, 9)),
-                                          ((6, 5, 3, 34), (2, 5))],
-                         ids=["20x13x64", "9x6x7", "6x5x3"])
-def test_offload_matches_device_path(pw, copy_out_env, shape, chunks, dtype, mode):
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("kind", list(KINDS))
+@pytest.mark.parametrize("shape,chunks", SHAPES, ids=["x".join(map(str, s[0][:3])) + "h%d" % s[0][3]
+                                                       for s in SHAPES])
+def test_offload_matches_oracle(pw, shape, chunks, kind, mode):
+    nx, ny, nz, h, seed = shape
+    dtype, compute, rk = KINDS[kind]
     pinned = mode != "pageable"
-    copy_out_env(mode == "pinned_runtime_copy")
-    nx, ny, nz, seed = shape
     fields, _, coef = host_case(nx, ny, nz, seed)
     tzc1, tzc2, tcx, tcy = coef
-    st = [oracle.pad_periodic(f, H) for f in fields]       # halo-filled storage on the host
+    st = [oracle.pad_periodic(inputs.round_storage(f, rk), h) for f in fields]   # host storage, FP64 values
+    ref = oracle.fwd(*st, tzc1, tzc2, tcx, tcy, h)
+    mag = oracle.fwd(*st, tzc1, tzc2, tcx, tcy, h, abs_bound=True)
     t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
-    dev_in = [torch.from_numpy(a).to(DEV, dtype) for a in st]
-    ref = [o.cpu() for o in pw.fwd(*dev_in, t1, t2, tcx, tcy, H)]
+    dev_ref = [o.cpu().double().numpy()
+               for o in pw.fwd(*[torch.from_numpy(a).to(DEV, dtype) for a in st], t1, t2, tcx, tcy, h,
+                               compute=compute)]
     host_in = [_host(a, dtype, pinned) for a in st]
+    inner = lambda a: a[h:-h, h:-h, h:-h]
     for chunk in chunks:
-        log("offload %s %s %s chunk %d" % (shape, dtype, mode, chunk))
+        log("offload %s h=%d %s %s chunk %d" % ((nx, ny, nz), h, kind, mode, chunk))
         outs = [torch.full(host_in[0].shape, float("nan"), dtype=dtype, pin_memory=pinned) for _ in range(3)]
-        ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, H, dtype, chunk), dtype=torch.uint8,
-                         device=DEV)
-        pw.fwd_host(*host_in, t1, t2, tcx, tcy, H, *outs, chunk, ws)
+        ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, h, dtype, chunk, compute=compute),
+                         dtype=torch.uint8, device=DEV)
+        with pw.tuning(copy_out="kernel" if mode == "pinned_copy_kernel" else "runtime"):
+            pw.fwd_host(*host_in, t1, t2, tcx, tcy, h, *outs, chunk, ws, compute=compute)
         torch.cuda.current_stream().synchronize()
-        for got, r in zip(outs, ref):
-            g = got.numpy()
-            rr = r.numpy()
-            assert np.array_equal(g[H:-H, H:-H], rr[H:-H, H:-H]), chunk   # interior columns incl. z halo
-            assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[-H:]))     # x halo planes untouched
-            assert np.all(np.isnan(g[:, :H])) and np.all(np.isnan(g[:, -H:]))  # y halo columns untouched
+        for q, got in enumerate(outs):
+            g = got.double().numpy()
+            assert within_bar(kind, inner(g), inner(ref[q]), inner(mag[q])), (chunk, q)
+            assert np.array_equal(g[h:-h, h:-h], dev_ref[q][h:-h, h:-h]), (chunk, q)  # incl. zero z halo
+            assert np.all(np.isnan(g[:h])) and np.all(np.isnan(g[-h:]))              # x halo planes
+            assert np.all(np.isnan(g[:, :h])) and np.all(np.isnan(g[:, -h:]))        # y halo columns
 
 
-@pytest.mark.parametrize("runtime_copy", [False, True], ids=["copy_kernel", "runtime_copy"])
-def test_offload_orders_on_callers_stream(pw, copy_out_env, runtime_copy):
-    """Work queued on the stream before the call (a device fill of a tensor
-    that is then copied into the pinned input) is seen by the offload, and
-    work queued after it (a copy reading the pinned outputs) sees the host
-    results."""
-    copy_out_env(runtime_copy)
-    nx, ny, nz, seed = 16, 12, 64, 33
+@pytest.mark.parametrize("copy_out", ["kernel", "runtime"])
+def test_offload_orders_on_callers_stream(pw, copy_out):
+    """Work queued on the stream before the call (a device copy into the
+    pinned inputs) is seen by the offload, and work queued after it (a copy
+    reading the pinned outputs) sees the host results, which match the
+    oracle bit for bit."""
+    nx, ny, nz, seed, h = 16, 12, 64, 33, 2
     fields, _, coef = host_case(nx, ny, nz, seed)
     tzc1, tzc2, tcx, tcy = coef
-    st = [oracle.pad_periodic(f, H) for f in fields]
+    st = [oracle.pad_periodic(f, h) for f in fields]
+    ref = oracle.fwd(*st, tzc1, tzc2, tcx, tcy, h)
     t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
-    ref = [o.cpu() for o in pw.fwd(*[torch.from_numpy(a).to(DEV) for a in st], t1, t2, tcx, tcy, H)]
     s = torch.cuda.Stream()
-    with torch.cuda.stream(s):
+    with torch.cuda.stream(s), pw.tuning(copy_out=copy_out):
         dev = [torch.from_numpy(a).to(DEV, non_blocking=False) for a in st]
         host_in = [torch.empty(a.shape, dtype=torch.float64, pin_memory=True) for a in st]
         for hsrc, d in zip(host_in, dev):
             hsrc.copy_(d, non_blocking=True)                 # queued on s before the offload
         outs = [torch.zeros(host_in[0].shape, dtype=torch.float64, pin_memory=True) for _ in range(3)]
-        ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, H, torch.float64, 5), dtype=torch.uint8,
+        ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, h, torch.float64, 5), dtype=torch.uint8,
                          device=DEV)
-        pw.fwd_host(*host_in, t1, t2, tcx, tcy, H, *outs, 5, ws)
+        pw.fwd_host(*host_in, t1, t2, tcx, tcy, h, *outs, 5, ws)
         back = [torch.empty_like(o, device=DEV) for o in outs]
         for b, o in zip(back, outs):
             b.copy_(o, non_blocking=True)                    # queued on s after the offload
     s.synchronize()
     for b, r in zip(back, ref):
-        assert np.array_equal(b.cpu().numpy()[H:-H, H:-H], r.numpy()[H:-H, H:-H])
+        bb = b.cpu().numpy()
+        assert np.array_equal(bb[h:-h, h:-h, h:-h], r[h:-h, h:-h, h:-h])
 
 
 def test_offload_argument_errors(pw):
-    shape = (8 + 2 * H, 6 + 2 * H, 64 + 2 * H)
+    h = 2
+    shape = (8 + 2 * h, 6 + 2 * h, 64 + 2 * h)
     host = [torch.zeros(shape, dtype=torch.float64) for _ in range(6)]
     t = torch.zeros(64, dtype=torch.float64, device=DEV)
-    need = pw.offload_workspace_bytes(shape, H, torch.float64, 3)
+    need = pw.offload_workspace_bytes(shape, h, torch.float64, 3)
     small = torch.empty(need - 8, dtype=torch.uint8, device=DEV)
     with pytest.raises(pw.PWError) as e:
-        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, *host[3:], 3, small)
+        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, h, *host[3:], 3, small)
     assert e.value.code == -4
     ws = torch.empty(need, dtype=torch.uint8, device=DEV)
     with pytest.raises(pw.PWError) as e:
-        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, host[0], host[4], host[5], 3, ws)
+        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, h, host[0], host[4], host[5], 3, ws)
     assert e.value.code == -2
     with pytest.raises(pw.PWError) as e:
-        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, H, *host[3:], 0, ws)
+        pw.fwd_host(*host[:3], t, t, -0.005, -0.005, h, *host[3:], 0, ws)
     assert e.value.code == -1
     # a device array in place of a host one is refused (the binding would
     # refuse it too, so call the C entry point directly)
     d = torch.zeros(shape, dtype=torch.float64, device=DEV)
     p = [pw._ptr(x) for x in host]
     rc = pw.lib.pw_advect_fwd_host(p[0], p[1], pw._ptr(d), pw._ptr(t), pw._ptr(t), -0.005, -0.005,
-                                   8, 6, 64, H, p[3], p[4], p[5], 3, pw._ptr(ws), need, 0, pw._stream())
+                                   8, 6, 64, h, p[3], p[4], p[5], 3, pw._ptr(ws), need, 0, pw._stream())
     assert rc == -1 and b"device memory" in pw.lib.pw_last_error()

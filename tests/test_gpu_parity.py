@@ -13,8 +13,6 @@ Tolerances (stated here and in the design notes):
     six terms at most six times, so 10 units of 2^-24 bound the arithmetic and
     the margin covers the rounding of tzc and tcx to FP32.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -201,19 +199,10 @@ def test_every_march_variant_matches_direct(pw, variant, dtype, shape):
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
     ref_f = run_fwd(pw, fields, coef, dtype, "direct", sentinel=False)
     ref_a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
-    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
-    os.environ["PW_MARCH_VARIANT"] = variant
-    os.environ["PW_MARCH_LX"] = "7"
-    try:
+    with pw.tuning(variant=variant, lx=7):
         got_f = run_fwd(pw, fields, coef, dtype, "march", sentinel=False)
         got_a = run_adj(pw, fields, lams, coef, dtype, "march", fused=True)
         got_g = run_adj(pw, fields, lams, coef, dtype, "march", fused=False)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
     for x, y in zip(ref_f + ref_a, got_f + got_a):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
     for x, y in zip(ref_a[3:], got_g):
@@ -282,18 +271,9 @@ def test_tall_columns_every_variant_matches_direct(pw, variant, dtype):
     fields, lams, coef = host_case(13, 11, 150, 15, lam_seed=65)
     ref_f = run_fwd(pw, fields, coef, dtype, "direct", sentinel=False)
     ref_a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
-    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
-    os.environ["PW_MARCH_VARIANT"] = variant
-    os.environ["PW_MARCH_LX"] = "4"
-    try:
+    with pw.tuning(variant=variant, lx=4):
         got_f = run_fwd(pw, fields, coef, dtype, "march", sentinel=True)
         got_a = run_adj(pw, fields, lams, coef, dtype, "march", fused=True)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
     for x, y in zip(ref_f + ref_a, got_f + got_a):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
     for g in got_f:   # every interior column fully written, halo columns untouched
@@ -303,7 +283,7 @@ def test_tall_columns_every_variant_matches_direct(pw, variant, dtype):
         assert np.all(np.isnan(g[:H])) and np.all(np.isnan(g[:, :H]))
 
 
-@pytest.mark.parametrize("variant", ["5", "6"])
+@pytest.mark.parametrize("variant", [5, 6])
 @pytest.mark.parametrize("halo", [1, 3])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_edge_wave_variants_other_halos(pw, variant, halo, dtype):
@@ -318,22 +298,9 @@ def test_edge_wave_variants_other_halos(pw, variant, halo, dtype):
     sl = [pw.pad_periodic(t, halo) for t in to_dev(lams, dtype)]
     t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
     res = {}
-    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
-    os.environ["PW_MARCH_VARIANT"] = variant
-    os.environ["PW_MARCH_LX"] = "5"
-    try:
-        for kernel in ("direct", "march"):
-            prev = pw.set_kernel(kernel)
-            try:
-                res[kernel] = [o.cpu().numpy() for o in pw.fwd_adj(*st, *sl, t1, t2, tcx, tcy, halo)]
-            finally:
-                pw.set_kernel(prev)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+    for kernel in ("direct", "march"):
+        with pw.tuning(kernel=kernel, variant=variant, lx=5):
+            res[kernel] = [o.cpu().numpy() for o in pw.fwd_adj(*st, *sl, t1, t2, tcx, tcy, halo)]
     inner_h = lambda a: a[halo:-halo, halo:-halo, halo:-halo]
     for a, b in zip(res["direct"], res["march"]):
         assert np.array_equal(inner_h(a), inner_h(b))
