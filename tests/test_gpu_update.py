@@ -8,7 +8,6 @@ results must equal the oracle's FP64 result rounded to float.  FP32 results
 are bounded by the forward's FP32 bound scaled by |beta| plus two roundings
 of the result.
 """
-import os
 
 import numpy as np
 import pytest
@@ -130,17 +129,8 @@ def test_update_f32_bound(pw, kernel, mode):
 def test_update_march_variants_match_direct(pw, variant, mode):
     fields, base, coef = host_case(45, 31, 64, 67, lam_seed=68)
     ref, _ = run(pw, "direct", mode, fields, base, coef, 0.29, torch.float64)
-    old = {k: os.environ.get(k) for k in ("PW_MARCH_VARIANT", "PW_MARCH_LX")}
-    os.environ["PW_MARCH_VARIANT"] = variant
-    os.environ["PW_MARCH_LX"] = "7"
-    try:
+    with pw.tuning(variant=variant, lx=7):
         got, _ = run(pw, "march", mode, fields, base, coef, 0.29, torch.float64)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
     for x, y in zip(ref, got):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
 
