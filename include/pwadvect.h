@@ -221,6 +221,28 @@ int pw_advect_fwd_host(const void *u, const void *v, const void *w,
                        int chunk, void *workspace, size_t workspace_bytes, int dtype, void *stream);
 
 /*
+ * pw_advect_fwd_host without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the three slab buffer sets live in a static scratch
+ * array of the library, pw_static_scratch_bytes() bytes (128 MiB) on each
+ * device the library runs on, held from module load until the process ends.
+ * Arguments, results and errors as for pw_advect_fwd_host, except that
+ * PW_ERR_SIZE means pw_offload_workspace_bytes(nx, ny, nz, halo, dtype,
+ * chunk) exceeds the static scratch (choose a smaller chunk).  The first call
+ * on a device looks up that device's address of the scratch and creates the
+ * copy streams and events (set-up); no call allocates device memory.  Calls
+ * on one device share its scratch, which keeps the last call's slabs: the
+ * library starts each call after the last copy out of the offload call
+ * queued before it on that device, so such calls never overlap.
+ */
+size_t pw_static_scratch_bytes(void);
+int pw_advect_fwd_host_static(const void *u, const void *v, const void *w,
+                              const double *tzc1, const double *tzc2, double tcx, double tcy,
+                              int nx, int ny, int nz, int halo,
+                              void *su, void *sv, void *sw,
+                              int chunk, int dtype, void *stream);
+
+/*
  * Periodic halo fill in place (the halo swap that precedes advection in each
  * timestep, section 2.1, for a domain that is periodic in x and y): copies
  * whole storage columns so that storage column (i, j) for i or j outside the

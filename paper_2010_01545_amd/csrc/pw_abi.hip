@@ -321,6 +321,76 @@ int check_one(const void* p, size_t bytes, size_t align, const char* name)
     return check_device(a, 1);
 }
 
+// pw_advect_fwd_host and its allocation-free variant: the slab buffers are
+// the caller's workspace, or (use_static) the library's static scratch, whose
+// calls are then ordered one after another on the device.
+int do_fwd_host(const char* name, const void* u, const void* v, const void* w, const double* tzc1,
+                const double* tzc2, double tcx, double tcy, int nx, int ny, int nz, int halo, void* su, void* sv,
+                void* sw, int chunk, void* workspace, size_t workspace_bytes, bool use_static, int dtype,
+                void* stream)
+{
+    Geom g;
+    size_t bytes;
+    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
+    if (rc) return rc;
+    if (chunk < 1) return fail(PW_ERR_ARG, "chunk=%d: need chunk >= 1", chunk);
+    if (chunk > nx) chunk = nx;
+    const size_t es = elem_size(dtype);
+    const size_t need = offload_workspace_bytes(g, chunk, es);
+    if (use_static) {
+        if (need > kStaticScratchBytes)
+            return fail(PW_ERR_SIZE, "%s: chunk %d needs %zu bytes of scratch; the static scratch holds %zu", name,
+                        chunk, need, kStaticScratchBytes);
+    } else {
+        if (!workspace) return fail(PW_ERR_ARG, "workspace is NULL");
+        if (workspace_bytes < need)
+            return fail(PW_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
+                        need);
+    }
+    const Arr in[3] = {{u, bytes, es, "u"}, {v, bytes, es, "v"}, {w, bytes, es, "w"}};
+    const Arr out[3] = {{su, bytes, es, "su"}, {sv, bytes, es, "sv"}, {sw, bytes, es, "sw"}};
+    rc = check_host_side(in, 3, out, 3);
+    if (rc) return rc;
+    const Arr host[6] = {in[0], in[1], in[2], out[0], out[1], out[2]};
+    rc = check_host_memory(host, 6);
+    if (rc) return rc;
+    const Arr dev[3] = {{tzc1, (size_t)nz * 8, 8, "tzc1"}, {tzc2, (size_t)nz * 8, 8, "tzc2"},
+                        {workspace, need, 16, "workspace"}};
+    const int ndev = use_static ? 2 : 3;
+    rc = check_host_side(dev, ndev, nullptr, 0);
+    if (rc) return rc;
+    rc = check_device(dev, ndev);
+    if (rc) return rc;
+    if (use_static) {
+        const hipError_t e = static_scratch_for_current_device(&workspace);
+        if (e != hipSuccess)
+            return fail(PW_ERR_HIP, "%s: looking up the static scratch: %s", name, hipGetErrorString(e));
+    }
+    // the slab kernels follow the same selection as pw_advect_fwd
+    Geom sg = g;
+    sg.nx = chunk;
+    const Arr ws[1] = {{workspace, need, 16, "workspace"}};
+    const int kern = with_types(dtype, [&](auto t, auto) { return resolve_kernel<decltype(t)>(sg, ws, 1); });
+    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and columns under 1 GiB");
+    // outputs go back through the runtime's copies unless the thread asked
+    // for the copy kernel and they are pinned host memory mapped into the
+    // device's address space
+    void* od[3] = {nullptr, nullptr, nullptr};
+    bool mapped = g_tune.copy_out == PW_COPY_OUT_KERNEL;
+    for (int f = 0; f < 3 && mapped; ++f) mapped = (od[f] = mapped_host(out[f].p, bytes)) != nullptr;
+    const char* what = "";
+    const bool march = kern == PW_KERNEL_MARCH;
+    const int e = with_types(dtype, [&](auto t, auto c) {
+        using T = decltype(t);
+        T* const o[3] = {(T*)od[0], (T*)od[1], (T*)od[2]};
+        return offload_fwd<T, decltype(c)>((const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, g, (T*)su,
+                                           (T*)sv, (T*)sw, mapped ? o : nullptr, chunk, workspace, march,
+                                           use_static, march_tune(), (hipStream_t)stream, &what);
+    });
+    if (e) return fail(PW_ERR_HIP, "%s: %s: %s", name, what, hipGetErrorString((hipError_t)e));
+    return launched(name);
+}
+
 }  // namespace
 
 extern "C" {
@@ -401,54 +471,18 @@ int pw_advect_fwd_host(const void* u, const void* v, const void* w, const double
                        double tcx, double tcy, int nx, int ny, int nz, int halo, void* su, void* sv, void* sw,
                        int chunk, void* workspace, size_t workspace_bytes, int dtype, void* stream)
 {
-    Geom g;
-    size_t bytes;
-    int rc = check_shape(nx, ny, nz, halo, dtype, g, bytes);
-    if (rc) return rc;
-    if (chunk < 1) return fail(PW_ERR_ARG, "chunk=%d: need chunk >= 1", chunk);
-    if (chunk > nx) chunk = nx;
-    const size_t es = elem_size(dtype);
-    const size_t need = offload_workspace_bytes(g, chunk, es);
-    if (!workspace) return fail(PW_ERR_ARG, "workspace is NULL");
-    if (workspace_bytes < need)
-        return fail(PW_ERR_SIZE, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes,
-                    need);
-    const Arr in[3] = {{u, bytes, es, "u"}, {v, bytes, es, "v"}, {w, bytes, es, "w"}};
-    const Arr out[3] = {{su, bytes, es, "su"}, {sv, bytes, es, "sv"}, {sw, bytes, es, "sw"}};
-    rc = check_host_side(in, 3, out, 3);
-    if (rc) return rc;
-    const Arr host[6] = {in[0], in[1], in[2], out[0], out[1], out[2]};
-    rc = check_host_memory(host, 6);
-    if (rc) return rc;
-    const Arr dev[3] = {{tzc1, (size_t)nz * 8, 8, "tzc1"}, {tzc2, (size_t)nz * 8, 8, "tzc2"},
-                        {workspace, need, 16, "workspace"}};
-    rc = check_host_side(dev, 3, nullptr, 0);
-    if (rc) return rc;
-    rc = check_device(dev, 3);
-    if (rc) return rc;
-    // the slab kernels follow the same selection as pw_advect_fwd
-    Geom sg = g;
-    sg.nx = chunk;
-    const Arr ws[1] = {{workspace, need, 16, "workspace"}};
-    const int kern = with_types(dtype, [&](auto t, auto) { return resolve_kernel<decltype(t)>(sg, ws, 1); });
-    if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and columns under 1 GiB");
-    // outputs go back through the runtime's copies unless the thread asked
-    // for the copy kernel and they are pinned host memory mapped into the
-    // device's address space
-    void* od[3] = {nullptr, nullptr, nullptr};
-    bool mapped = g_tune.copy_out == PW_COPY_OUT_KERNEL;
-    for (int f = 0; f < 3 && mapped; ++f) mapped = (od[f] = mapped_host(out[f].p, bytes)) != nullptr;
-    const char* what = "";
-    const bool march = kern == PW_KERNEL_MARCH;
-    const int e = with_types(dtype, [&](auto t, auto c) {
-        using T = decltype(t);
-        T* const o[3] = {(T*)od[0], (T*)od[1], (T*)od[2]};
-        return offload_fwd<T, decltype(c)>((const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, g, (T*)su,
-                                           (T*)sv, (T*)sw, mapped ? o : nullptr, chunk, workspace, march,
-                                           march_tune(), (hipStream_t)stream, &what);
-    });
-    if (e) return fail(PW_ERR_HIP, "pw_advect_fwd_host: %s: %s", what, hipGetErrorString((hipError_t)e));
-    return launched("pw_advect_fwd_host");
+    return do_fwd_host("pw_advect_fwd_host", u, v, w, tzc1, tzc2, tcx, tcy, nx, ny, nz, halo, su, sv, sw, chunk,
+                       workspace, workspace_bytes, false, dtype, stream);
+}
+
+size_t pw_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int pw_advect_fwd_host_static(const void* u, const void* v, const void* w, const double* tzc1,
+                              const double* tzc2, double tcx, double tcy, int nx, int ny, int nz, int halo,
+                              void* su, void* sv, void* sw, int chunk, int dtype, void* stream)
+{
+    return do_fwd_host("pw_advect_fwd_host_static", u, v, w, tzc1, tzc2, tcx, tcy, nx, ny, nz, halo, su, sv, sw,
+                       chunk, nullptr, 0, true, dtype, stream);
 }
 
 int pw_halo_periodic(void* storage, int nx, int ny, int nz, int halo, int dtype, void* stream)

@@ -70,8 +70,16 @@ void launch_stream_copy(const void* const* src, void* const* dst, int n, size_t 
 // holds the device addresses of su, sv, sw when they are mapped pinned host
 // memory and the copy kernel was asked for (it then writes them), else
 // nullptr (runtime copies).
+// With after_previous the call's copies and kernels start after the last copy
+// out of the offload call queued before it on the device (its buffers may be
+// the same).
 size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es);
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
                 const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
-                MarchTune tune, hipStream_t stream, const char** what);
+                bool after_previous, MarchTune tune, hipStream_t stream, const char** what);
+
+// Static scratch of pw_advect_fwd_host_static (pw_offload.hip): its size and
+// the current device's address of it (looked up once per device).
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+hipError_t static_scratch_for_current_device(void** out);

@@ -126,6 +126,37 @@ hipError_t queues_for_current_device(DeviceQueues** out)
 
 }  // namespace
 
+// Scratch of the allocation-free entry point pw_advect_fwd_host_static: its
+// three slab buffer sets live in this array instead of a caller's workspace.
+// Every device the library runs on holds its own copy from module load until
+// the process ends.  In host code `scratch` names a host-side stand-in, never
+// the device memory: host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t static_scratch_for_current_device(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 // Bytes of one slab buffer set: three input and three output slab arrays of
 // chunk + 2h planes each.
 size_t offload_slab_set_bytes(const Geom& g, int chunk, size_t es)
@@ -141,7 +172,7 @@ size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es)
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
                 const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
-                MarchTune tune, hipStream_t stream, const char** what)
+                bool after_previous, MarchTune tune, hipStream_t stream, const char** what)
 {
     DeviceQueues* q = nullptr;
     hipError_t e = queues_for_current_device(&q);
@@ -152,6 +183,12 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
     // one enqueue at a time per process: the internal streams and events are
     // shared, and each wait captures the event's latest record when it is queued
     std::lock_guard<std::mutex> lock(g_enqueue_mutex);
+    // a call whose buffers another call may still use (the static scratch)
+    // starts after the last copy out of the call queued before it
+    if (after_previous) {
+        if ((e = hipStreamWaitEvent(q->h2d, q->end_out, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+        if ((e = hipStreamWaitEvent(stream, q->end_out, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+    }
     const size_t plane = (size_t)g.sx;                       // elements per storage plane
     const size_t slab = (size_t)(chunk + 2 * g.h) * plane;   // elements per slab array
     T* base = (T*)workspace;
@@ -223,8 +260,8 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
 
 #define PW_OFFLOAD_INSTANCE(T, C)                                                                            \
     template int offload_fwd<T, C>(const T*, const T*, const T*, const double*, const double*, double, double, \
-                                   const Geom&, T*, T*, T*, T* const*, int, void*, bool, MarchTune, hipStream_t, \
-                                   const char**);
+                                   const Geom&, T*, T*, T*, T* const*, int, void*, bool, bool, MarchTune,      \
+                                   hipStream_t, const char**);
 PW_OFFLOAD_INSTANCE(double, double)
 PW_OFFLOAD_INSTANCE(float, float)
 PW_OFFLOAD_INSTANCE(float, double)

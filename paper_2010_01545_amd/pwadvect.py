@@ -46,6 +46,9 @@ lib.pw_pad_periodic.argtypes = [_vp, _vp] + [_i] * 5 + [_vp]
 lib.pw_fill_uniform.argtypes = [_vp] + [_i] * 4 + [ctypes.c_ulonglong, _i, _d, _i, _i, _vp]
 lib.pw_advect_fwd_host.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _vp, ctypes.c_size_t,
                                                                           _i, _vp]
+lib.pw_advect_fwd_host_static.argtypes = [_vp] * 5 + [_d, _d] + [_i] * 4 + [_vp] * 3 + [_i, _i, _vp]
+lib.pw_static_scratch_bytes.argtypes = []
+lib.pw_static_scratch_bytes.restype = ctypes.c_size_t
 lib.pw_offload_workspace_bytes.argtypes = [_i] * 6
 lib.pw_offload_workspace_bytes.restype = ctypes.c_size_t
 lib.pw_set_kernel.argtypes = [_i]
@@ -54,6 +57,7 @@ lib.pw_get_tuning.argtypes = [_i, ctypes.POINTER(_i)]
 lib.pw_stream_copy.argtypes = [_vp, _vp, _i, ctypes.c_size_t, _i, _vp]
 lib.pw_last_error.restype = ctypes.c_char_p
 for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_advect_fwd_update",
+           "pw_advect_fwd_host_static",
            "pw_halo_periodic", "pw_pad_periodic", "pw_fill_uniform", "pw_stream_copy", "pw_set_kernel",
            "pw_get_kernel", "pw_set_tuning", "pw_get_tuning", "pw_version"):
     getattr(lib, _f).restype = ctypes.c_int
@@ -198,6 +202,29 @@ def fwd_host(u, v, w, tzc1, tzc2, tcx, tcy, halo, su, sv, sw, chunk, workspace, 
                                   _ptr(workspace), workspace.numel() * workspace.element_size(),
                                   _dtype_code(u, compute), _stream()))
     return su, sv, sw
+
+
+def fwd_host_static(u, v, w, tzc1, tzc2, tcx, tcy, halo, su, sv, sw, chunk, compute=None):
+    """fwd_host with the library's static scratch in place of a workspace
+    (allocates no device memory); tzc1/tzc2 must already be device tensors
+    of nz doubles.  Raises PWError (PW_ERR_SIZE) when ``chunk`` needs more
+    than static_scratch_bytes()."""
+    nx, ny, nz = _grid(u, halo)
+    for t in (u, v, w, su, sv, sw):
+        if t.is_cuda or not t.is_contiguous() or t.shape != u.shape or t.dtype != u.dtype:
+            raise ValueError("fwd_host_static takes contiguous host tensors of one storage shape and dtype")
+    for t in (tzc1, tzc2):
+        if not (torch.is_tensor(t) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.shape == (nz,)):
+            raise ValueError("tzc1/tzc2 must be contiguous float64 device tensors of length nz")
+    _check(lib.pw_advect_fwd_host_static(_ptr(u), _ptr(v), _ptr(w), _ptr(tzc1), _ptr(tzc2), float(tcx),
+                                         float(tcy), nx, ny, nz, halo, _ptr(su), _ptr(sv), _ptr(sw), int(chunk),
+                                         _dtype_code(u, compute), _stream()))
+    return su, sv, sw
+
+
+def static_scratch_bytes():
+    return int(lib.pw_static_scratch_bytes())
 
 
 def halo_periodic(storage, halo):
