@@ -41,6 +41,7 @@
 // 8 XCDs; ids are remapped so that each XCD receives a contiguous range of
 // strips, so the halo columns shared by neighbouring strips are read through
 // the same L2.
+#include <atomic>
 #include <type_traits>
 
 #include "pw_half.h"
@@ -495,30 +496,62 @@ struct Launch {
     int LX, nstrips, nchunk, nblocks, grid;
 };
 
-// Segment length: the caller's choice (lx > 0), else segments of up to 128
-// planes (measured best at 4096 x 4096 x 64), shorter ones on smaller grids
-// so that at least kTargetBlocks workgroups exist (about 32 per compute unit)
-// and the last round of workgroups is a small part of the launch.  A segment
-// reads its two end planes once more than the interior ones, so segments are
-// kept at kMinLX planes or more.
-constexpr int kTargetBlocks = 8192;
+// Segment length: the caller's choice (lx > 0), else the length that
+// minimises a simple cost model of the launch.  With `slots` workgroups
+// resident on the device at once, the segments run in about
+// ceil(nblocks / slots) rounds, and a segment of LX planes costs about
+// LX + kSegmentCost planes: it reads its two end planes beyond the planes it
+// computes and fills its prefetch ring before the first step.  The model,
+// fitted to sweeps on MI355X, picks 128-plane segments at 4096 x 4096 x 64
+// and 10 to 26 planes at 256 x 256 x 64.  Ties go to the longer segment.
 constexpr int kMinLX = 4;
 constexpr int kMaxLX = 128;
+constexpr int kSegmentCost = 5;
 
-Launch plan(const Geom& g, int TY, int lx)
+Launch plan(const Geom& g, int TY, int lx, int slots)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
     l.nchunk = g.nz <= NZ ? 1 : (g.nz + kChunk - 1) / kChunk;
+    const long long cols = (long long)l.nstrips * l.nchunk;
     if (lx <= 0) {
-        const long long want = ((long long)g.nx * l.nstrips * l.nchunk + kTargetBlocks - 1) / kTargetBlocks;
-        lx = want < kMinLX ? kMinLX : (want > kMaxLX ? kMaxLX : (int)want);
+        long long best = -1;
+        const int hi = g.nx < kMaxLX ? g.nx : kMaxLX;
+        const int lo = hi < kMinLX ? hi : kMinLX;
+        for (int c = hi; c >= lo; --c) {
+            const long long blocks = cols * ((g.nx + c - 1) / c);
+            const long long cost = ((blocks + slots - 1) / slots) * (c + kSegmentCost);
+            if (best < 0 || cost < best) {
+                best = cost;
+                lx = c;
+            }
+        }
     }
     l.LX = lx;
     const int nseg = (g.nx + lx - 1) / lx;
-    l.nblocks = l.nstrips * l.nchunk * nseg;
+    l.nblocks = (int)(cols * nseg);
     l.grid = ((l.nblocks + 7) / 8) * 8;
     return l;
+}
+
+// Compute units of the current device (cached per device).
+int compute_units()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+            (void)hipGetLastError();
+            n = 256;
+        }
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
 }
 
 // Strip width, prefetch depth, halo carriers and LDS cap of each variant.
@@ -548,9 +581,20 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, hipStream_t s)
     constexpr int TY = kTY[V], D = kD[V];
     constexpr bool EH = kEH[V];
     if constexpr (lds_bytes<T, C, NF, TY>() <= kLdsCap[V]) {
-        const Launch l = plan(g, TY, lx);
-        hipLaunchKernelGGL((march_kernel<T, C, NF, WS, WG, TY, D, EH, UPD>), dim3(l.grid),
-                           dim3(64 * (EH ? TY : TY + 2)), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
+        constexpr int threads = 64 * (EH ? TY : TY + 2);
+        const auto kernel = march_kernel<T, C, NF, WS, WG, TY, D, EH, UPD>;
+        // workgroups of this kernel that one compute unit holds at once (its
+        // registers and LDS decide), queried once per instantiation
+        static const int per_cu = [&] {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1) {
+                (void)hipGetLastError();
+                n = 1;
+            }
+            return n;
+        }();
+        const Launch l = plan(g, TY, lx, per_cu * compute_units());
+        hipLaunchKernelGGL(kernel, dim3(l.grid), dim3(threads), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
     } else {
         go<T, C, NF, WS, WG, 0, UPD>(m, g, lx, s);
     }
