@@ -115,8 +115,20 @@ enum {
                                   type and output set [-1] */
     PW_TUNE_MARCH_LX = 2,      /* x-planes per marching workgroup, or 0 to choose
                                   from the grid [0] */
-    PW_TUNE_COPY_OUT = 3       /* how pw_advect_fwd_host returns the source terms,
+    PW_TUNE_COPY_OUT = 3,      /* how pw_advect_fwd_host returns the source terms,
                                   PW_COPY_OUT_* [PW_COPY_OUT_RUNTIME] */
+    PW_TUNE_BLOCK_ORDER = 4    /* order of the x-marching workgroups over the
+                                  strips: PW_ORDER_XCD, or G in
+                                  1..PW_ORDER_MAX_GROUP for groups of G
+                                  neighbouring strips per XCD, the 8 XCDs
+                                  interleaved group by group (1: natural
+                                  order), or -1 for the measured default of
+                                  each kernel [-1] */
+};
+enum {
+    PW_ORDER_XCD = 0,       /* each of the 8 XCDs takes one contiguous range of strips */
+    PW_ORDER_NATURAL = 1,   /* neighbouring strips on all XCDs at once */
+    PW_ORDER_MAX_GROUP = 65536
 };
 enum { PW_MARCH_VARIANTS = 7 };
 enum {

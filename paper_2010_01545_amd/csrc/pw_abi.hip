@@ -22,10 +22,11 @@ struct Tuning {
     int variant = -1;                 // < 0: default variant
     int lx = 0;                       // 0: segment length from the grid
     int copy_out = PW_COPY_OUT_RUNTIME;
+    int order = -1;                   // < 0: default block order, 0: XCD ranges, G: groups of G
 };
 thread_local Tuning g_tune;
 
-MarchTune march_tune() { return MarchTune{g_tune.variant, g_tune.lx}; }
+MarchTune march_tune() { return MarchTune{g_tune.variant, g_tune.lx, g_tune.order}; }
 
 int fail(int code, const char* fmt, ...)
 {
@@ -595,6 +596,11 @@ int pw_set_tuning(int knob, int value)
             return fail(PW_ERR_ARG, "unknown copy-out mode %d", value);
         g_tune.copy_out = value;
         break;
+    case PW_TUNE_BLOCK_ORDER:
+        if (value < -1 || value > PW_ORDER_MAX_GROUP)
+            return fail(PW_ERR_ARG, "block order %d outside -1..%d", value, PW_ORDER_MAX_GROUP);
+        g_tune.order = value;
+        break;
     default:
         return fail(PW_ERR_ARG, "unknown tuning knob %d", knob);
     }
@@ -609,6 +615,7 @@ int pw_get_tuning(int knob, int* value)
     case PW_TUNE_MARCH_VARIANT: *value = g_tune.variant; break;
     case PW_TUNE_MARCH_LX: *value = g_tune.lx; break;
     case PW_TUNE_COPY_OUT: *value = g_tune.copy_out; break;
+    case PW_TUNE_BLOCK_ORDER: *value = g_tune.order; break;
     default: return fail(PW_ERR_ARG, "unknown tuning knob %d", knob);
     }
     return ok();

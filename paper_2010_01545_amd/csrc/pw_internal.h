@@ -44,11 +44,13 @@ template <typename T, typename C> void launch_adj_direct(const AdjArgs<T>& a, co
 
 // x-marching kernels (any nz >= 2, halo <= 32, 16-byte aligned arrays,
 // columns shorter than 1 GiB).  MarchTune carries the calling thread's
-// choice of variant (< 0: the default for the type pair and output set) and
-// segment length in planes (0: chosen from the grid).
+// choice of variant (< 0: the default for the type pair and output set),
+// segment length in planes (0: chosen from the grid) and block order (< 0:
+// the default; 0: XCD ranges; 1: natural).
 struct MarchTune {
     int variant;
     int lx;
+    int order;
 };
 template <typename T> bool march_supported(const Geom& g);
 template <typename T, typename C>

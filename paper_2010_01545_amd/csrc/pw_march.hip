@@ -38,9 +38,20 @@
 // three-plane ring (step p deposits plane p+2).  One barrier per step.
 //
 // Block order.  Consecutive workgroup ids are dispatched round-robin over the
-// 8 XCDs; ids are remapped so that each XCD receives a contiguous range of
-// strips, so the halo columns shared by neighbouring strips are read through
-// the same L2.
+// 8 XCDs (hardware id b runs on XCD b % 8).  The work items (strip fastest,
+// then z-chunk, then segment) are dealt to the XCDs in groups of G
+// consecutive items, XCDs interleaved group by group:
+//   * G = ceil(blocks / 8) ("XCD ranges"): each XCD takes one contiguous
+//     range of strips, so halo columns shared by neighbouring strips are
+//     read through the same L2, but the 8 XCDs march in 8 different parts
+//     of the grid;
+//   * G = 1 ("natural"): the workgroups resident at any time are
+//     neighbouring strips of the same segments on all XCDs, so the device
+//     sweeps the same x-planes together (long runs of neighbouring addresses
+//     in flight), but every halo column is read through two L2s;
+//   * G in between keeps most halo columns inside one XCD's L2 while the
+//     device still sweeps one window of the grid.
+// Which is fastest depends on the kernel and on where the arrays lie in HBM.
 #include <atomic>
 #include <type_traits>
 
@@ -223,7 +234,7 @@ struct MarchArgs {
 // same with b = (u, v, w), whose centre values are already in the ring.
 template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, bool EH, int UPD = 0>
 __global__ void __launch_bounds__(64 * (EH ? TY : TY + 2))
-march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks)
+march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks, int group)
 {
     static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
     static_assert(!EH || TY >= 2, "the two halo columns belong to different edge waves");
@@ -249,10 +260,11 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
 
-    // XCD-aware remap: hardware id b runs on XCD b % 8; give each XCD a
-    // contiguous range of logical ids (strip fastest).
-    const int per = (nblocks + 7) >> 3;
-    const int L = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    // block order (uniform): groups of `group` consecutive work items per XCD,
+    // XCDs interleaved group by group (the grid is a multiple of 8 * group,
+    // so every item below nblocks is taken exactly once)
+    const int xcd = (int)(blockIdx.x & 7), gslot = (int)(blockIdx.x >> 3);
+    const int L = ((gslot / group) * 8 + xcd) * group + gslot % group;
     if (L >= nblocks) return;
     const int strip = L % nstrips;
     const int chunk = (L / nstrips) % nchunk;
@@ -493,7 +505,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
 }
 
 struct Launch {
-    int LX, nstrips, nchunk, nblocks, grid;
+    int LX, nstrips, nchunk, nblocks, group, grid;
 };
 
 // Segment length: the caller's choice (lx > 0), else the length that
@@ -508,7 +520,7 @@ constexpr int kMinLX = 4;
 constexpr int kMaxLX = 128;
 constexpr int kSegmentCost = 5;
 
-Launch plan(const Geom& g, int TY, int lx, int slots)
+Launch plan(const Geom& g, int TY, int lx, int slots, int order)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
@@ -530,7 +542,10 @@ Launch plan(const Geom& g, int TY, int lx, int slots)
     l.LX = lx;
     const int nseg = (g.nx + lx - 1) / lx;
     l.nblocks = (int)(cols * nseg);
-    l.grid = ((l.nblocks + 7) / 8) * 8;
+    // order > 0: groups of `order` items per XCD; 0: one contiguous range each
+    const int per = (l.nblocks + 7) / 8;
+    l.group = order > 0 && order < per ? order : per;
+    l.grid = ((l.nblocks + 8 * l.group - 1) / (8 * l.group)) * (8 * l.group);
     return l;
 }
 
@@ -576,7 +591,7 @@ constexpr int lds_bytes()
 static_assert(kLdsCap[0] <= 163840 && kLdsCap[4] <= 163840 && kLdsCap[6] <= 163840, "LDS of one compute unit");
 
 template <typename T, typename C, int NF, bool WS, bool WG, int V, int UPD>
-void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, hipStream_t s)
+void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, int order, hipStream_t s)
 {
     constexpr int TY = kTY[V], D = kD[V];
     constexpr bool EH = kEH[V];
@@ -593,34 +608,54 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, hipStream_t s)
             }
             return n;
         }();
-        const Launch l = plan(g, TY, lx, per_cu * compute_units());
-        hipLaunchKernelGGL(kernel, dim3(l.grid), dim3(threads), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks);
+        const Launch l = plan(g, TY, lx, per_cu * compute_units(), order);
+        hipLaunchKernelGGL(kernel, dim3(l.grid), dim3(threads), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks,
+                           l.group);
     } else {
-        go<T, C, NF, WS, WG, 0, UPD>(m, g, lx, s);
+        go<T, C, NF, WS, WG, 0, UPD>(m, g, lx, order, s);
     }
 }
 
-// Default variant per type pair, field count, output set and update form,
-// from interleaved sweeps on MI355X at 4096 x 4096 x 64:
-//   * 14-column strips with halo waves wherever the registers allow 16
-//     wavefronts (HBM-bound FP64 and FP32 kernels, 16-bit forward kernels);
-//   * six-field kernels with FP64 arithmetic: 6-column strips (150-190
-//     registers allow 8 or 12 wavefronts per unit); for FP32 storage the
-//     adjoint in 10-column strips (11% faster) and the fused pass in
-//     8-column strips with edge waves (9% faster: its arithmetic sets the
-//     pace, and 8 computing waves keep all four SIMDs equally busy);
-//   * 16-bit storage: the adjoint and the accumulating update in 8-column
-//     strips with edge waves (8-10% faster), the bfloat16 fused pass in
-//     16-column strips with edge waves (5%).
+// Default variant and block order per type pair, field count, output set
+// and update form.  Chosen from sweeps of every (variant, order) pair in one
+// process on the same arrays on MI355X at 4096 x 4096 x 64, and for the
+// close candidates from six re-allocations of the arrays in one process (the
+// arrays' placement in HBM moves a kernel by up to 15% between allocations;
+// one candidate order can be fast in one placement and slow in the next):
+//   * the FP64 and FP32 forward and Euler update: 16-column strips with edge
+//     waves in natural order (FP64 9.96 ms mean over six placements, range
+//     9.22-10.28, against 10.02 ms for 14-column strips with halo waves in
+//     XCD ranges and 10.59 ms, range 9.14-11.48, for those in natural order;
+//     FP32 5.01 against 5.13 ms);
+//   * the FP64 fused pass and adjoint: 6-column strips with halo waves in XCD
+//     ranges (every alternative within 2% on the mean).  Their 150-240
+//     registers allow only 8 or 12 wavefronts per unit;
+//   * FP32 fused pass and adjoint, and the accumulating update of both: 14
+//     columns with halo waves in XCD ranges (the FP32 fused pass runs at the
+//     speed of a plain copy of its twelve streams; the FP64 accumulating
+//     update spills in 16-column strips with edge waves);
+//   * FP32 storage with FP64 arithmetic: the adjoint in 10-column strips (11%
+//     faster than 6) and the fused pass in 8-column strips with edge waves
+//     (9%: its arithmetic sets the pace, and 8 computing waves keep all four
+//     SIMDs equally busy), XCD ranges;
+//   * 16-bit storage, XCD ranges: the adjoint and the accumulating update in
+//     8-column strips with edge waves (8-10% faster), the bfloat16 fused
+//     pass in 16-column strips with edge waves (5%), the rest in 14-column
+//     strips with halo waves.
 // Deeper prefetch (D = 4) measured no faster.  A thread's tuning state
-// (pw_set_tuning) can name another variant, for sweeps.
+// (pw_set_tuning) can name another variant or order, for sweeps.
+template <typename T, typename C, int NF, bool WS, int UPD>
+constexpr bool edge16_natural()
+{
+    return NF == 3 && UPD != 1 && sizeof(T) == sizeof(C) && sizeof(T) >= 4;
+}
+
 template <typename T, typename C, int NF, bool WS, int UPD>
 int default_variant()
 {
-    if (NF == 6 && sizeof(C) == 8) {
-        if (sizeof(T) == 4) return WS ? 5 : 4;
-        return 0;
-    }
+    if (edge16_natural<T, C, NF, WS, UPD>()) return 6;
+    if (NF == 6 && sizeof(T) == 8) return 0;
+    if (NF == 6 && sizeof(C) == 8) return WS ? 5 : 4;
     if (sizeof(T) == 2) {
         if (NF == 6 && !WS) return 5;
         if (NF == 3 && UPD == 1) return 5;
@@ -629,18 +664,27 @@ int default_variant()
     return 2;
 }
 
+// Default block order of the default variant: 0 for XCD ranges, G > 0 for
+// groups of G strips per XCD (1: natural order).
+template <typename T, typename C, int NF, bool WS, int UPD>
+int default_order()
+{
+    return edge16_natural<T, C, NF, WS, UPD>() ? 1 : 0;
+}
+
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t s)
 {
     const int v = (t.variant >= 0 && t.variant < kVariants) ? t.variant : default_variant<T, C, NF, WS, UPD>();
+    const int order = t.order >= 0 ? t.order : default_order<T, C, NF, WS, UPD>();
     switch (v) {
-    case 1: go<T, C, NF, WS, WG, 1, UPD>(m, g, t.lx, s); break;
-    case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, t.lx, s); break;
-    case 3: go<T, C, NF, WS, WG, 3, UPD>(m, g, t.lx, s); break;
-    case 4: go<T, C, NF, WS, WG, 4, UPD>(m, g, t.lx, s); break;
-    case 5: go<T, C, NF, WS, WG, 5, UPD>(m, g, t.lx, s); break;
-    case 6: go<T, C, NF, WS, WG, 6, UPD>(m, g, t.lx, s); break;
-    default: go<T, C, NF, WS, WG, 0, UPD>(m, g, t.lx, s); break;
+    case 1: go<T, C, NF, WS, WG, 1, UPD>(m, g, t.lx, order, s); break;
+    case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, t.lx, order, s); break;
+    case 3: go<T, C, NF, WS, WG, 3, UPD>(m, g, t.lx, order, s); break;
+    case 4: go<T, C, NF, WS, WG, 4, UPD>(m, g, t.lx, order, s); break;
+    case 5: go<T, C, NF, WS, WG, 5, UPD>(m, g, t.lx, order, s); break;
+    case 6: go<T, C, NF, WS, WG, 6, UPD>(m, g, t.lx, order, s); break;
+    default: go<T, C, NF, WS, WG, 0, UPD>(m, g, t.lx, order, s); break;
     }
 }
 

@@ -22,9 +22,10 @@ LIB_PATH = os.path.join(HERE, "libpwadvect.so")
 PW_F64, PW_F32, PW_F32_F64, PW_F16, PW_BF16 = 0, 1, 2, 3, 4
 KERNELS = {"auto": 0, "direct": 1, "march": 2}
 # tuning knobs of the calling thread (pw_set_tuning)
-TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT = 0, 1, 2, 3
+TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT, TUNE_BLOCK_ORDER = 0, 1, 2, 3, 4
 MARCH_VARIANTS = 7
 COPY_OUT = {"runtime": 0, "kernel": 1}
+ORDERS = {"default": -1, "xcd": 0, "natural": 1}   # or an int G: groups of G strips per XCD
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
           -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
 
@@ -297,9 +298,11 @@ class tuning:
     """Context manager: set tuning knobs of the calling thread for a block
     and restore them afterwards, e.g. ``with pw.tuning(variant=3, lx=7):``.
     Keywords: kernel ('auto', 'direct', 'march'), variant (-1..6), lx (planes
-    per marching workgroup, 0 = automatic), copy_out ('runtime', 'kernel')."""
+    per marching workgroup, 0 = automatic), copy_out ('runtime', 'kernel'),
+    order ('default', 'xcd', 'natural', or an int G: groups of G neighbouring
+    strips per XCD)."""
 
-    def __init__(self, kernel=None, variant=None, lx=None, copy_out=None):
+    def __init__(self, kernel=None, variant=None, lx=None, copy_out=None, order=None):
         self.want = []
         if kernel is not None:
             self.want.append((TUNE_KERNEL, KERNELS[kernel]))
@@ -309,6 +312,8 @@ class tuning:
             self.want.append((TUNE_MARCH_LX, int(lx)))
         if copy_out is not None:
             self.want.append((TUNE_COPY_OUT, COPY_OUT[copy_out]))
+        if order is not None:
+            self.want.append((TUNE_BLOCK_ORDER, ORDERS[order] if isinstance(order, str) else int(order)))
         self.saved = []
 
     def __enter__(self):

@@ -105,10 +105,11 @@ def test_fused_separate_and_kernels_agree(pw, kind):
     for a, b in zip(results["direct"], results["march"]):
         assert np.array_equal(oracle.interior(a, H), oracle.interior(b, H))
     for v in MARCH_VARIANTS:
-        with pw.tuning(variant=v, lx=7):
-            f = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *c, H))
-        for a, b in zip(results["direct"], f):
-            assert np.array_equal(oracle.interior(a, H), oracle.interior(b, H)), v
+        for order in ("xcd", "natural"):
+            with pw.tuning(variant=v, lx=7, order=order):
+                f = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *c, H))
+            for a, b in zip(results["direct"], f):
+                assert np.array_equal(oracle.interior(a, H), oracle.interior(b, H)), (v, order)
 
 
 @pytest.mark.parametrize("kind", list(TYPES))

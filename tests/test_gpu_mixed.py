@@ -111,13 +111,14 @@ def test_fused_equals_separate(pw, kernel):
         assert np.array_equal(interior(a), interior(b))
 
 
+@pytest.mark.parametrize("order", ["xcd", "natural"])
 @pytest.mark.parametrize("variant", MARCH_VARIANTS)
-def test_every_march_variant_matches_direct(pw, variant):
+def test_every_march_variant_matches_direct(pw, variant, order):
     fields, lams, coef = host_case(45, 31, 64, 49, lam_seed=50)
     st, sl = dev_f32(pw, as_f32(fields)), dev_f32(pw, as_f32(lams))
     args = coef_dev(coef) + (coef[2], coef[3], H)
     ref = with_kernel(pw, "direct", lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
-    with pw.tuning(variant=variant, lx=7):
+    with pw.tuning(variant=variant, lx=7, order=order):
         got = with_kernel(pw, "march", lambda: pw.fwd_adj(*st, *sl, *args, compute=F64))
         got_g = with_kernel(pw, "march", lambda: pw.adj(*st, *sl, *args, compute=F64))
     for a, b in zip(ref, got):

@@ -185,21 +185,23 @@ def test_march_and_direct_agree_bitwise(pw, dtype):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
 
 
+@pytest.mark.parametrize("order", ["xcd", "natural", 3])
 @pytest.mark.parametrize("shape", [(45, 31, 64, 14), (12, 17, 40, 16)], ids=lambda s: "x".join(map(str, s[:3])))
 @pytest.mark.parametrize("variant", MARCH_VARIANTS)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_every_march_variant_matches_direct(pw, variant, dtype, shape):
+def test_every_march_variant_matches_direct(pw, variant, dtype, shape, order):
     """Each strip-width / prefetch-depth / halo-carrier variant of the
-    x-marching kernel (and a short march length, so several x-segments meet)
-    gives the direct kernel's bits, forward, adjoint and fused.  ny = 31 and
-    17 leave last strips one column and several columns narrower than every
-    strip width, and a one-column strip."""
+    x-marching kernel, in three block orders (XCD ranges, natural, groups of
+    3 strips per XCD) and with a short march length (so
+    several x-segments meet), gives the direct kernel's bits, forward, adjoint
+    and fused.  ny = 31 and 17 leave last strips one column and several
+    columns narrower than every strip width, and a one-column strip."""
     nx, ny, nz, seed = shape
-    log("variant %s %s %s" % (variant, dtype, shape))
+    log("variant %s %s %s %s" % (variant, dtype, shape, order))
     fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 50)
     ref_f = run_fwd(pw, fields, coef, dtype, "direct", sentinel=False)
     ref_a = run_adj(pw, fields, lams, coef, dtype, "direct", fused=True)
-    with pw.tuning(variant=variant, lx=7):
+    with pw.tuning(variant=variant, lx=7, order=order):
         got_f = run_fwd(pw, fields, coef, dtype, "march", sentinel=False)
         got_a = run_adj(pw, fields, lams, coef, dtype, "march", fused=True)
         got_g = run_adj(pw, fields, lams, coef, dtype, "march", fused=False)

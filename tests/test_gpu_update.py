@@ -124,12 +124,13 @@ def test_update_f32_bound(pw, kernel, mode):
     check_layout(o)
 
 
+@pytest.mark.parametrize("order", ["xcd", "natural"])
 @pytest.mark.parametrize("variant", MARCH_VARIANTS)
 @pytest.mark.parametrize("mode", MODES)
-def test_update_march_variants_match_direct(pw, variant, mode):
+def test_update_march_variants_match_direct(pw, variant, mode, order):
     fields, base, coef = host_case(45, 31, 64, 67, lam_seed=68)
     ref, _ = run(pw, "direct", mode, fields, base, coef, 0.29, torch.float64)
-    with pw.tuning(variant=variant, lx=7):
+    with pw.tuning(variant=variant, lx=7, order=order):
         got, _ = run(pw, "march", mode, fields, base, coef, 0.29, torch.float64)
     for x, y in zip(ref, got):
         assert np.array_equal(oracle.interior(x, H), oracle.interior(y, H))
