@@ -627,9 +627,13 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, int order, hipStream_t
 //     9.22-10.28, against 10.02 ms for 14-column strips with halo waves in
 //     XCD ranges and 10.59 ms, range 9.14-11.48, for those in natural order;
 //     FP32 5.01 against 5.13 ms);
-//   * the FP64 fused pass and adjoint: 6-column strips with halo waves in XCD
-//     ranges (every alternative within 2% on the mean).  Their 150-240
-//     registers allow only 8 or 12 wavefronts per unit;
+//   * the FP64 fused pass: 8-column strips with edge waves in natural order
+//     (at 4096 x 4096 x 64 19.61 ms mean over six placements, against 20.00
+//     ms in XCD ranges and 19.95 ms for 6-column strips with halo waves; at
+//     256 x 256 x 64 and 512 x 512 x 64 10% faster than the latter, as all 8
+//     waves compute); the FP64 adjoint: 6-column strips with halo waves in
+//     XCD ranges.  Their 150-240 registers allow only 8 or 12 wavefronts per
+//     unit;
 //   * FP32 fused pass and adjoint, and the accumulating update of both: 14
 //     columns with halo waves in XCD ranges (the FP32 fused pass runs at the
 //     speed of a plain copy of its twelve streams; the FP64 accumulating
@@ -650,11 +654,23 @@ constexpr bool edge16_natural()
     return NF == 3 && UPD != 1 && sizeof(T) == sizeof(C) && sizeof(T) >= 4;
 }
 
+// Grids whose six arrays of the forward fit in the 256 MB Infinity Cache
+// are not HBM-bound: there the forward kernels that default to 16-column
+// strips use 8 computing waves in 8-column strips with edge waves in XCD
+// ranges instead (256 x 256 x 64 FP64: 0.0377 against 0.0398 ms).
+constexpr long long kCacheResidentBytes = 256LL << 20;
+
+template <typename T>
+bool cache_resident(const Geom& g)
+{
+    return 6LL * g.Sx * g.sx * (long long)sizeof(T) <= kCacheResidentBytes;
+}
+
 template <typename T, typename C, int NF, bool WS, int UPD>
 int default_variant()
 {
     if (edge16_natural<T, C, NF, WS, UPD>()) return 6;
-    if (NF == 6 && sizeof(T) == 8) return 0;
+    if (NF == 6 && sizeof(T) == 8) return WS ? 5 : 0;
     if (NF == 6 && sizeof(C) == 8) return WS ? 5 : 4;
     if (sizeof(T) == 2) {
         if (NF == 6 && !WS) return 5;
@@ -669,14 +685,16 @@ int default_variant()
 template <typename T, typename C, int NF, bool WS, int UPD>
 int default_order()
 {
-    return edge16_natural<T, C, NF, WS, UPD>() ? 1 : 0;
+    return (edge16_natural<T, C, NF, WS, UPD>() || (NF == 6 && WS && sizeof(T) == 8)) ? 1 : 0;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t s)
 {
-    const int v = (t.variant >= 0 && t.variant < kVariants) ? t.variant : default_variant<T, C, NF, WS, UPD>();
-    const int order = t.order >= 0 ? t.order : default_order<T, C, NF, WS, UPD>();
+    const bool small = edge16_natural<T, C, NF, WS, UPD>() && cache_resident<T>(g);
+    const int v = (t.variant >= 0 && t.variant < kVariants) ? t.variant
+                : small ? 5 : default_variant<T, C, NF, WS, UPD>();
+    const int order = t.order >= 0 ? t.order : small ? 0 : default_order<T, C, NF, WS, UPD>();
     switch (v) {
     case 1: go<T, C, NF, WS, WG, 1, UPD>(m, g, t.lx, order, s); break;
     case 2: go<T, C, NF, WS, WG, 2, UPD>(m, g, t.lx, order, s); break;
