@@ -161,7 +161,8 @@ def path_record(path, esize, cells, times_ms):
     }
 
 
-COPY_BLOCKS = (0, 1024, 2048, 4096)   # launch shapes of the streaming copy (0: one pass)
+# launch shapes of the streaming copy: (bytes per thread and array, workgroups; 0 = one pass)
+COPY_SHAPES = ((4, 0), (8, 0), (16, 0), (16, 2048))
 
 
 def copy_reference(pw, torch, g, reps=5):
@@ -173,24 +174,24 @@ def copy_reference(pw, torch, g, reps=5):
     forward kernels on the same arrays, so that their ratio compares like with
     like."""
     nbytes = g.f[0].numel() * g.f[0].element_size()
-    rec = {"kernel": "pw_stream_copy: 16-byte loads and stores, every thread reads its unit of each source "
-                     "then writes each destination; storage arrays of %d bytes" % nbytes}
+    rec = {"kernel": "pw_stream_copy: every thread reads its unit of each source then writes each destination; "
+                     "storage arrays of %d bytes" % nbytes}
     for tag, src, dst, path in (("6R6W", g.f + g.l, g.s + g.g, "fused"), ("3R3W", g.f, g.s, "fwd")):
         shapes = {}
-        for b in COPY_BLOCKS:
-            pw.stream_copy(src, dst, b)
-            ms = time_launches(torch, lambda: pw.stream_copy(src, dst, b), reps)
-            shapes["blocks_%d" % b] = {"ms": sum(ms) / len(ms),
-                                        "GBps": 2 * len(src) * nbytes / (sum(ms) / len(ms) * 1e-3) / 1e9}
+        for unit, b in COPY_SHAPES:
+            pw.stream_copy(src, dst, b, unit)
+            ms = time_launches(torch, lambda: pw.stream_copy(src, dst, b, unit), reps)
+            shapes["unit_%d_blocks_%d" % (unit, b)] = {
+                "ms": sum(ms) / len(ms), "GBps": 2 * len(src) * nbytes / (sum(ms) / len(ms) * 1e-3) / 1e9}
         best = min(shapes, key=lambda k: shapes[k]["ms"])
-        b = int(best.split("_")[1])
+        unit, b = (int(x) for x in best.split("_")[1::2])
         # interleaved: copy, kernel, copy, kernel ...
         tc, tk = [], []
         for _ in range(reps):
-            tc += time_launches(torch, lambda: pw.stream_copy(src, dst, b), 1)
+            tc += time_launches(torch, lambda: pw.stream_copy(src, dst, b, unit), 1)
             tk += time_launches(torch, lambda: g.launch(pw, path), 1)
         mc, mk = sum(tc) / len(tc), sum(tk) / len(tk)
-        rec[tag] = {"ms": mc, "GBps": 2 * len(src) * nbytes / (mc * 1e-3) / 1e9, "blocks": b,
+        rec[tag] = {"ms": mc, "GBps": 2 * len(src) * nbytes / (mc * 1e-3) / 1e9, "unit": unit, "blocks": b,
                     "launch_shapes": shapes,
                     "interleaved_%s_f64_ms" % path: mk,
                     "%s_f64_time_fraction_of_copy" % path: mc / mk}
@@ -395,6 +396,7 @@ def main():
     ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64, "
                     "or the streaming copy of 3 or 6 storage arrays (copy3, copy6)")
     ap.add_argument("--copy-blocks", type=int, default=0, help="launch shape of --only copy3/copy6")
+    ap.add_argument("--copy-unit", type=int, default=4, help="bytes per thread and array of --only copy3/copy6")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -432,7 +434,7 @@ def main():
         src, dst = (g.f + g.l)[:n], (g.s + g.g)[:n]
         torch.cuda.synchronize()
         for _ in range(args.warmup + args.steps):
-            pw.stream_copy(src, dst, args.copy_blocks)
+            pw.stream_copy(src, dst, args.copy_blocks, args.copy_unit)
         torch.cuda.synchronize()
         log("bench: profile run of %s done" % args.only)
         return

@@ -291,19 +291,20 @@ int pw_fill_uniform(void *storage, int nx, int ny, int nz, int halo,
 /*
  * Measurement utility (not part of the scheme): one launch of a plain
  * streaming copy kernel that copies src[q] to dst[q] for q < narrays, each
- * `bytes` long, with 16-byte accesses, every thread reading its 16-byte units
- * of all sources before writing them to all destinations.  It moves the
- * streams of the advection calls over arrays of the same size (3 arrays: the
- * forward's 3 reads and 3 writes; 6 arrays: those of pw_advect_fwd_adj) and
- * so is the achievable-bandwidth reference their HBM rate is read against.
- * src and dst are HOST arrays of narrays device pointers, each 16-byte
- * aligned; bytes must be a multiple of 16; 1 <= narrays <= 8; no destination
- * may overlap any array.  blocks = 0 launches one 256-thread workgroup per
- * 4 KiB of each array (each thread copies one 16-byte unit per array), blocks
- * > 0 launches that many workgroups striding over the arrays.  Asynchronous
- * on `stream`.  Errors: PW_ERR_ARG, PW_ERR_ALIGN, PW_ERR_ALIAS, PW_ERR_HIP.
+ * `bytes` long, in units of `unit` bytes (4, 8 or 16), every thread reading
+ * its unit of all sources before writing it to all destinations.  It moves
+ * the streams of the advection calls over arrays of the same size (3 arrays:
+ * the forward's 3 reads and 3 writes; 6 arrays: those of pw_advect_fwd_adj)
+ * and so is the achievable-bandwidth reference their rate is read against.
+ * src and dst are HOST arrays of narrays device pointers, each aligned to the
+ * unit; bytes must be a multiple of the unit; 1 <= narrays <= 8; no
+ * destination may overlap any array.  blocks = 0 launches one 256-thread
+ * workgroup per 256 units of each array (each thread copies one unit per
+ * array; the unit count must stay below 2^32), blocks > 0 launches that many
+ * workgroups striding over the arrays.  Asynchronous on `stream`.  Errors:
+ * PW_ERR_ARG, PW_ERR_ALIGN, PW_ERR_ALIAS, PW_ERR_SIZE, PW_ERR_HIP.
  */
-int pw_stream_copy(const void *const *src, void *const *dst, int narrays, size_t bytes, int blocks,
+int pw_stream_copy(const void *const *src, void *const *dst, int narrays, size_t bytes, int unit, int blocks,
                    void *stream);
 
 /*

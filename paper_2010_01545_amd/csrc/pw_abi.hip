@@ -545,20 +545,23 @@ int pw_fill_uniform(void* storage, int nx, int ny, int nz, int halo, unsigned lo
     return launched("pw_fill_uniform");
 }
 
-int pw_stream_copy(const void* const* src, void* const* dst, int narrays, size_t bytes, int blocks, void* stream)
+int pw_stream_copy(const void* const* src, void* const* dst, int narrays, size_t bytes, int unit, int blocks,
+                   void* stream)
 {
     if (!src || !dst) return fail(PW_ERR_ARG, "src and dst must not be NULL");
     if (narrays < 1 || narrays > 8) return fail(PW_ERR_ARG, "narrays=%d outside 1..8", narrays);
-    if (bytes % 16) return fail(PW_ERR_ARG, "bytes=%zu is not a multiple of 16", bytes);
+    if (unit != 4 && unit != 8 && unit != 16) return fail(PW_ERR_ARG, "unit=%d: need 4, 8 or 16", unit);
+    if (bytes % (size_t)unit) return fail(PW_ERR_ARG, "bytes=%zu is not a multiple of the unit %d", bytes, unit);
     if (blocks < 0) return fail(PW_ERR_ARG, "blocks=%d: need 0 or more", blocks);
-    if (blocks == 0 && (bytes / 16 + 255) / 256 > 0xffffffffULL)
-        return fail(PW_ERR_SIZE, "one pass over %zu bytes needs more than 2^32 workgroups", bytes);
+    // one pass: one thread per unit, and the grid's thread count must fit 32 bits
+    if (blocks == 0 && bytes / (size_t)unit > 0xffffff00ULL)
+        return fail(PW_ERR_SIZE, "one pass over %zu bytes in %d-byte units needs 2^32 threads or more", bytes, unit);
     static const char* const sn[8] = {"src[0]", "src[1]", "src[2]", "src[3]", "src[4]", "src[5]", "src[6]", "src[7]"};
     static const char* const dn[8] = {"dst[0]", "dst[1]", "dst[2]", "dst[3]", "dst[4]", "dst[5]", "dst[6]", "dst[7]"};
     Arr in[8], out[8];
     for (int q = 0; q < narrays; ++q) {
-        in[q] = Arr{src[q], bytes, 16, sn[q]};
-        out[q] = Arr{dst[q], bytes, 16, dn[q]};
+        in[q] = Arr{src[q], bytes, (size_t)unit, sn[q]};
+        out[q] = Arr{dst[q], bytes, (size_t)unit, dn[q]};
     }
     int rc = check_host_side(in, narrays, out, narrays);
     if (rc) return rc;
@@ -570,7 +573,7 @@ int pw_stream_copy(const void* const* src, void* const* dst, int narrays, size_t
     rc = check_device(all, 2 * narrays);
     if (rc) return rc;
     (void)hipGetLastError();
-    launch_stream_copy(src, dst, narrays, bytes, blocks, (hipStream_t)stream);
+    launch_stream_copy(src, dst, narrays, bytes, unit, blocks, (hipStream_t)stream);
     return launched("pw_stream_copy");
 }
 

@@ -55,7 +55,7 @@ lib.pw_offload_workspace_bytes.restype = ctypes.c_size_t
 lib.pw_set_kernel.argtypes = [_i]
 lib.pw_set_tuning.argtypes = [_i, _i]
 lib.pw_get_tuning.argtypes = [_i, ctypes.POINTER(_i)]
-lib.pw_stream_copy.argtypes = [_vp, _vp, _i, ctypes.c_size_t, _i, _vp]
+lib.pw_stream_copy.argtypes = [_vp, _vp, _i, ctypes.c_size_t, _i, _i, _vp]
 lib.pw_last_error.restype = ctypes.c_char_p
 for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_advect_fwd_update",
            "pw_advect_fwd_host_static",
@@ -262,11 +262,12 @@ def fill_uniform(storage, halo, seed, field_id, amp=10.0, zero_lids=False):
     return storage
 
 
-def stream_copy(src, dst, blocks=0):
+def stream_copy(src, dst, blocks=0, unit=4):
     """One launch of the library's plain streaming copy: dst[q] <- src[q] for
     lists of equally sized contiguous device tensors (the bandwidth reference
-    of the advection kernels).  ``blocks`` = 0: one 16-byte unit per thread
-    and array; > 0: that many workgroups striding over the arrays."""
+    of the advection kernels), in ``unit``-byte units (4, 8 or 16).
+    ``blocks`` = 0: one unit per thread and array; > 0: that many workgroups
+    striding over the arrays."""
     if len(src) != len(dst) or not 1 <= len(src) <= 8:
         raise ValueError("1..8 source and destination tensors")
     nbytes = src[0].numel() * src[0].element_size()
@@ -276,7 +277,8 @@ def stream_copy(src, dst, blocks=0):
     n = len(src)
     sp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in src])
     dp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in dst])
-    _check(lib.pw_stream_copy(ctypes.cast(sp, _vp), ctypes.cast(dp, _vp), n, nbytes, int(blocks), _stream()))
+    _check(lib.pw_stream_copy(ctypes.cast(sp, _vp), ctypes.cast(dp, _vp), n, nbytes, int(unit), int(blocks),
+                              _stream()))
 
 
 def get_tuning(knob):

@@ -252,20 +252,24 @@ def test_library_reads_no_environment():
 # ---------------------------------------------------------------- streaming copy reference
 def test_stream_copy_checks(lib):
     vp = ctypes.c_void_p
-    lib.pw_stream_copy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, vp]
+    lib.pw_stream_copy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp]
 
-    def call(src, dst, n, nbytes, blocks=0):
+    def call(src, dst, n, nbytes, blocks=0, unit=16):
         s = (vp * len(src))(*src)
         d = (vp * len(dst))(*dst)
-        return lib.pw_stream_copy(ctypes.cast(s, vp), ctypes.cast(d, vp), n, nbytes, blocks, None)
+        return lib.pw_stream_copy(ctypes.cast(s, vp), ctypes.cast(d, vp), n, nbytes, unit, blocks, None)
 
     src, dst = ADDR[:3], ADDR[3:6]
-    assert lib.pw_stream_copy(None, None, 3, 4096, 0, None) == PW_ERR_ARG
+    assert lib.pw_stream_copy(None, None, 3, 4096, 4, 0, None) == PW_ERR_ARG
     assert call(src, dst, 0, 4096) == PW_ERR_ARG
     assert call(ADDR[:9], ADDR[:9], 9, 4096) == PW_ERR_ARG
     assert call(src, dst, 3, 4100) == PW_ERR_ARG                       # not a multiple of 16
+    assert call(src, dst, 3, 4098, unit=4) == PW_ERR_ARG               # not a multiple of 4
+    assert call(src, dst, 3, 4096, unit=2) == PW_ERR_ARG               # no 2-byte unit
     assert call(src, dst, 3, 4096, -1) == PW_ERR_ARG
     assert call([ADDR[0] + 8] + src[1:], dst, 3, 4096) == PW_ERR_ALIGN
+    assert call([ADDR[0] + 4] + src[1:], dst, 3, 4096, unit=8) == PW_ERR_ALIGN
     assert call(src, [dst[0], dst[1], src[2] + 16], 3, 4096) == PW_ERR_ALIAS   # dst overlaps a source
     assert call(src, [dst[0], dst[0] + 4080, dst[2]], 3, 4096) == PW_ERR_ALIAS  # two destinations overlap
     assert call([0] + src[1:], dst, 3, 4096) == PW_ERR_ARG             # NULL entry
+    assert call(src, dst, 3, (1 << 34) + (1 << 33), unit=4) == PW_ERR_SIZE   # 2^32 or more units in one pass
