@@ -91,25 +91,31 @@ def measured_traffic(kernel_name, workload):
 
 
 class Grid:
-    def __init__(self, pw, torch, nx, ny, nz, h, dtype, seed, with_lambda, compute=None):
+    """The arrays of one grid: u, v, w [, lu, lv, lw], su, sv, sw [, gu, gv,
+    gw].  pooled: views into one allocation (pwadvect.alloc_fields, the
+    layout the headline uses); else one allocation per array."""
+
+    def __init__(self, pw, torch, nx, ny, nz, h, dtype, seed, with_lambda, compute=None, pooled=True):
         self.nx, self.ny, self.nz, self.h = nx, ny, nz, h
         self.compute = compute
         self.cells = nx * ny * nz
         shape = (nx + 2 * h, ny + 2 * h, nz + 2 * h)
         dev = torch.device("cuda:0")
-        mk = lambda: torch.empty(shape, dtype=dtype, device=dev)
-        self.f = [mk() for _ in range(3)]
+        n = 12 if with_lambda else 6
+        if pooled:
+            arrs = pw.alloc_fields(n, shape, dtype, device=dev)
+        else:
+            arrs = [torch.empty(shape, dtype=dtype, device=dev) for _ in range(n)]
+        self.f = arrs[0:3]
+        self.l = arrs[3:6] if with_lambda else []
+        self.s = arrs[6:9] if with_lambda else arrs[3:6]
+        self.g = arrs[9:12] if with_lambda else []
         for fid, t in enumerate(self.f):
             pw.fill_uniform(t, h, seed, fid, 10.0, zero_lids=(fid == 2))
             pw.halo_periodic(t, h)
-        self.l = []
-        if with_lambda:
-            self.l = [mk() for _ in range(3)]
-            for q, t in enumerate(self.l):
-                pw.fill_uniform(t, h, seed, 3 + q, 1.0, False)
-                pw.halo_periodic(t, h)
-        self.s = [mk() for _ in range(3)]
-        self.g = [mk() for _ in range(3)] if with_lambda else []
+        for q, t in enumerate(self.l):
+            pw.fill_uniform(t, h, seed, 3 + q, 1.0, False)
+            pw.halo_periodic(t, h)
         from paper_2010_01545_amd import inputs
         tzc1, tzc2, self.tcx, self.tcy = inputs.coefficients(nz)
         self.t1 = torch.from_numpy(tzc1).to(dev)
@@ -391,6 +397,8 @@ def main():
     ap.add_argument("--no-paths", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-offload", action="store_true")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip the FP64 record over separately allocated arrays (same kernels, same grid)")
     ap.add_argument("--no-medium", action="store_true",
                     help="skip the cache-resident 256x256x64 record (its launches share the kernels' names)")
     ap.add_argument("--only", default=None, help="profile helper: run only this path/dtype, e.g. fused:f64, "
@@ -479,6 +487,22 @@ def main():
             log("bench: %s f64 %.2f ms" % (p, paths[p + "_f64"]["ms_avg"]))
     del g
     torch.cuda.empty_cache()
+
+    # the same FP64 launches over twelve separately allocated arrays: their
+    # speed depends on where each allocation lands in HBM
+    separate = None
+    if not args.no_paths and not args.no_separate:
+        g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True, pooled=False)
+        separate = {"layout": "one allocation per array"}
+        for p in ("fused", "fwd"):
+            g.launch(pw, p)
+            separate[p + "_f64"] = path_record(p, 8, cells, time_launches(torch, lambda: g.launch(pw, p),
+                                                                          args.paths_reps))
+            separate[p + "_f64"]["time_vs_pooled"] = separate[p + "_f64"]["ms_avg"] / paths[p + "_f64"]["ms_avg"]
+        log("bench: separately allocated arrays: fused f64 %.2f ms, fwd f64 %.2f ms" % (
+            separate["fused_f64"]["ms_avg"], separate["fwd_f64"]["ms_avg"]))
+        del g
+        torch.cuda.empty_cache()
     if not args.no_paths:
         g = Grid(pw, torch, nx, ny, nz, h, torch.float32, seed, True)
         for p in ("fwd", "adj", "fused"):
@@ -561,10 +585,12 @@ def main():
         "dtype": "f64", "data": "synthetic (counter-based U(-10,10) winds, U(-1,1) multipliers)",
         "config": {"workload": "%s %dx%dx%d halo %d, FP64 fused forward + adjoint"
                    % (args.workload, nx, ny, nz, h), "nx": nx, "ny": ny, "nz": nz, "halo": h,
-                   "cells": cells, "kernel": args.kernel},
+                   "cells": cells, "kernel": args.kernel,
+                   "layout": "pooled: each grid's arrays are views into one allocation"},
         "roofline": roofline,
         "paths": paths,
         "copy_reference": copy_ref,
+        "separate_allocations": separate,
         "precision_workload": precision,
         "medium_cache_resident": medium,
         "source_hash": kernel_source_hash(),

@@ -87,3 +87,27 @@ def test_stream_copy_copies_exactly(pw, n, unit, blocks):
     for s, d in zip(src, dst_full):
         assert torch.equal(d[:nbytes], s)
         assert torch.all(d[nbytes:] == 0xA5)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.float16])
+def test_pooled_fields_give_the_same_bits(pw, dtype):
+    """The forward and fused passes over arrays carved from one allocation
+    (alloc_fields) give the bits they give over separately allocated arrays."""
+    nx, ny, nz, h = 21, 18, 64, H
+    log("pooled fields %s" % dtype)
+    tzc1, tzc2, tcx, tcy = inputs.coefficients(nz)
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    shape = (nx + 2 * h, ny + 2 * h, nz + 2 * h)
+    pool = pw.alloc_fields(15, shape, dtype)
+    sep = [torch.empty(shape, dtype=dtype, device=DEV) for _ in range(15)]
+    for arrs in (pool, sep):
+        for q in range(6):
+            pw.fill_uniform(arrs[q], h, 11, q, 10.0 if q < 3 else 1.0, zero_lids=(q == 2))
+            pw.halo_periodic(arrs[q], h)
+        for t in arrs[6:]:
+            t.zero_()
+        pw.fwd(*arrs[:3], t1, t2, tcx, tcy, h, *arrs[12:15])
+        pw.fwd_adj(*arrs[:6], t1, t2, tcx, tcy, h, out=arrs[6:12])
+    torch.cuda.synchronize()
+    for a, b in zip(pool, sep):
+        assert torch.equal(a, b)
