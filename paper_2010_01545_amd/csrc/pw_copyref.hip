@@ -2,10 +2,11 @@
 // HBM rate of the advection kernels is read against.  It moves the same
 // streams as an advection call (n arrays read, n written, each of one storage
 // array's size) with nothing else to do: every thread reads its unit (4, 8
-// or 16 bytes) of every source before writing it to every destination.
-// Measured on MI355X for three FP64 storage arrays of 4096 x 4096 x 64:
-// 4-byte units in 256-thread workgroups 8.57 ms, 8-byte units in 128-thread
-// workgroups 9.06 ms, 16-byte units 9.6-9.7 ms (one pass or striding).
+// or 16 bytes) of every source before writing it to every destination, in
+// 256-thread workgroups.  Measured on MI355X for three FP64 storage arrays of
+// 4096 x 4096 x 64 in one pass: 4-byte units 8.49-8.58 ms, 8-byte units
+// 9.46 ms, 16-byte units 8.99 ms; 16-byte units in 2048 striding workgroups
+// 9.78 ms.
 #include "pw_internal.h"
 
 namespace {
