@@ -118,7 +118,13 @@ enum {
     PW_TUNE_MARCH_VARIANT = 1, /* x-marching variant 0..PW_MARCH_VARIANTS-1 (strip
                                   width, prefetch depth, halo carriers), or -1 for
                                   the measured default of each storage/arithmetic
-                                  type and output set [-1] */
+                                  type and output set [-1].  Variants 0..6 hold
+                                  one wavefront per column and cut columns of
+                                  more than 64 levels into z-chunks; variant
+                                  PW_MARCH_VARIANTS-1 holds a column of 65..256
+                                  levels in 2 or 4 wavefronts of one workgroup
+                                  (the default for such columns; for other
+                                  columns it selects the default variant) */
     PW_TUNE_MARCH_LX = 2,      /* x-planes per marching workgroup, or 0 to choose
                                   from the grid [0] */
     PW_TUNE_COPY_OUT = 3,      /* how pw_advect_fwd_host returns the source terms,
@@ -136,7 +142,7 @@ enum {
     PW_ORDER_NATURAL = 1,   /* neighbouring strips on all XCDs at once */
     PW_ORDER_MAX_GROUP = 65536
 };
-enum { PW_MARCH_VARIANTS = 7 };
+enum { PW_MARCH_VARIANTS = 8 };
 enum {
     PW_COPY_OUT_RUNTIME = 0, /* the HIP runtime's device-to-host copies */
     PW_COPY_OUT_KERNEL = 1   /* a copy kernel writing pinned host outputs that are

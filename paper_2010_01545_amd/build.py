@@ -112,9 +112,9 @@ def _march_args(mangled):
 
 def march_resource_table():
     """Markdown table of the x-marching kernels' compile-time resources."""
-    lines = ["| T | C | NF | WS | WG | TY | D | EH | UPD | VGPRs | SGPRs | VGPR spill | SGPR spill | "
+    lines = ["| T | C | NF | WS | WG | TY | D | EH | UPD | ZW | VGPRs | SGPRs | VGPR spill | SGPR spill | "
              "scratch B/lane | LDS B/WG | waves/SIMD |",
-             "|" + "---|" * 16]
+             "|" + "---|" * 17]
     for r in resource_usage("pw_march.hip"):
         a = _march_args(r["name"])
         if not a:

@@ -17,10 +17,16 @@
 //     ring.  With TY a multiple of 4 the arithmetic spreads evenly over the
 //     four SIMDs of a compute unit, which pays where the arithmetic, not HBM,
 //     sets the pace.
-// Taller columns are cut into z-chunks of 62 levels, one chunk per
-// workgroup: lane l holds level 62 c - 1 + l, lanes 0 and 63 are the chunk's
-// halo levels (loaded, never stored), so the z-neighbours of lanes 1..62
-// still come from wavefront shifts.
+// Columns of 65 to 256 levels are held by ZW = 2 or 4 wavefronts of one
+// workgroup, wave z holding levels 64 z .. 64 z + 63.  Their z-neighbours
+// come from the LDS ring instead of wavefront shifts: it then holds whole
+// columns, with a zero entry below level 0 and above the top, and keeps
+// three planes of every field, so that plane p+1 of a neighbouring wave's
+// levels is there when step p needs it.  Taller columns still are cut into
+// z-chunks of 62 levels, one chunk per workgroup: lane l holds level
+// 62 c - 1 + l, lanes 0 and 63 are the chunk's halo levels (loaded, never
+// stored), so the z-neighbours of lanes 1..62 still come from wavefront
+// shifts.
 //
 // Reuse.  Each field (u, v, w and, for the adjoint, lu, lv, lw) is read from
 // HBM once per cell:
@@ -232,11 +238,14 @@ struct MarchArgs {
 // b streamed through the register ring like the fields (b may be the output
 // itself: each element is read planes before the same wave writes it); 2 the
 // same with b = (u, v, w), whose centre values are already in the ring.
-template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, bool EH, int UPD = 0>
-__global__ void __launch_bounds__(64 * (EH ? TY : TY + 2))
+// ZW: wavefronts per column (1, or 2 or 4 for columns of up to 128 or 256
+// levels, whose z-neighbours then come from the LDS ring).
+template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, bool EH, int UPD = 0, int ZW = 1>
+__global__ void __launch_bounds__(64 * (EH ? TY : TY + 2) * ZW)
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks, int group)
 {
     static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
+    static_assert(ZW == 1 || ZW == 2 || ZW == 4, "one, two or four wavefronts per column");
     static_assert(!EH || TY >= 2, "the two halo columns belong to different edge waves");
     static_assert(UPD == 0 || (NF == 3 && WS && !WG), "the update form is a forward-only epilogue");
     constexpr int NCOL = TY + 2;    // LDS slots
@@ -251,13 +260,22 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
     constexpr int U = (D + 3 <= 6 && sizeof(T) < 8 && !EH) ? 6 : D + 3;
     constexpr int NR = NF + (UPD == 1 ? 3 : 0);   // ring rows: fields, then base arrays
     using W = work_t<T, C>;
-    __shared__ W s_uw[2 * NT][2][NCOL][NZ];
-    __shared__ W s_v[NT][3][NCOL][NZ];
+    // ZL: z-neighbours from the LDS ring, which then holds whole columns
+    // (entry 1 + k for level k, entries 0 and LZ - 1 zero) and three planes of
+    // the u- and w-type fields as of the v-type ones
+    constexpr bool ZL = ZW > 1;
+    constexpr int LZ = ZL ? NZ * ZW + 2 : NZ;
+    constexpr int UWS = ZL ? 3 : 2;
+    __shared__ W s_uw[2 * NT][UWS][NCOL][LZ];
+    __shared__ W s_v[NT][3][NCOL][LZ];
 
     // the wave index is uniform over a wavefront: keep it (and every address
     // part derived from it) in scalar registers, so that a global access is a
-    // scalar base plus the lane offset
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // scalar base plus the lane offset.  With ZW > 1 the ZW wavefronts of a
+    // column are consecutive: level block zw of column wave `wave`.
+    const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int zw = ZL ? wave_id % ZW : 0;
+    const int wave = ZL ? wave_id / ZW : wave_id;
     const int lane = threadIdx.x & 63;
 
     // block order (uniform): groups of `group` consecutive work items per XCD,
@@ -295,14 +313,17 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
     };
     // level of this lane; loads at levels outside 0..nz-1 are out of range
     // (read zero), stores only from the lanes the chunk owns
-    const int k = nchunk == 1 ? lane : chunk * kChunk - 1 + lane;
-    const bool own = nchunk == 1 || (lane >= 1 && lane <= kChunk);
+    const int k = ZL ? NZ * zw + lane : nchunk == 1 ? lane : chunk * kChunk - 1 + lane;
+    const bool own = ZL || nchunk == 1 || (lane >= 1 && lane <= kChunk);
+    const int lk = ZL ? 1 + k : lane;   // this lane's LDS entry
     const unsigned voff = (k >= 0 && k < g.nz) ? (unsigned)(g.h + k) * (unsigned)sizeof(T) : kOutOfRange;
     const unsigned vst = own ? voff : kOutOfRange;
     // z-halo levels of an output column: lanes 0..h-1 bottom (first chunk),
     // h..2h-1 top (last chunk)
-    const unsigned vpad = (lane < g.h && chunk == 0) ? (unsigned)lane * (unsigned)sizeof(T)
-                        : (lane >= g.h && lane < 2 * g.h && chunk == nchunk - 1)
+    const bool first_z = ZL ? zw == 0 : chunk == 0;
+    const bool last_z = ZL ? zw == ZW - 1 : chunk == nchunk - 1;
+    const unsigned vpad = (lane < g.h && first_z) ? (unsigned)lane * (unsigned)sizeof(T)
+                        : (lane >= g.h && lane < 2 * g.h && last_z)
                               ? (unsigned)(g.nz + lane) * (unsigned)sizeof(T) : kOutOfRange;
 
     // Multipliers are used with their level masks applied (see
@@ -340,7 +361,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
 #pragma unroll
         for (int t = 0; t < D + 2; ++t) {
             const W x = ld(f, i0 - 1 + t, 0, ring_bytes(f, i0 - 1 + t));
-            R[f][t] = (f < NF && t < (f % 3 == 1 ? 3 : 2)) ? mask(f, widen<T, W>(x)) : x;
+            R[f][t] = (f < NF && t < ((f % 3 == 1 || ZL) ? 3 : 2)) ? mask(f, widen<T, W>(x)) : x;
         }
     W H[NF][U];
     if (halo) {
@@ -363,11 +384,15 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int t = f / 3;
-            if (f % 3 == 0) s_uw[2 * t][0][slot][lane] = R[f][1];
-            if (f % 3 == 2) s_uw[2 * t + 1][0][slot][lane] = R[f][1];
+            if (f % 3 == 0) s_uw[2 * t][0][slot][lk] = R[f][1];
+            if (f % 3 == 2) s_uw[2 * t + 1][0][slot][lk] = R[f][1];
+            if constexpr (ZL) {
+                if (f % 3 == 0) s_uw[2 * t][1][slot][lk] = R[f][2];
+                if (f % 3 == 2) s_uw[2 * t + 1][1][slot][lk] = R[f][2];
+            }
             if (f % 3 == 1) {
-                s_v[t][0][slot][lane] = R[f][1];
-                s_v[t][1][slot][lane] = R[f][2];
+                s_v[t][0][slot][lk] = R[f][1];
+                s_v[t][1][slot][lk] = R[f][2];
             }
         }
         if (halo) {
@@ -375,12 +400,26 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
             for (int f = 0; f < NF; ++f) {
                 const int t = f / 3;
                 const W h1 = mask(f, widen<T, W>(H[f][1]));
-                if (f % 3 == 0) s_uw[2 * t][0][hslot][lane] = h1;
-                if (f % 3 == 2) s_uw[2 * t + 1][0][hslot][lane] = h1;
-                if (f % 3 == 1) {
-                    s_v[t][0][hslot][lane] = h1;
-                    s_v[t][1][hslot][lane] = mask(f, widen<T, W>(H[f][2]));
+                const W h2 = mask(f, widen<T, W>(H[f][2]));
+                if (f % 3 == 0) s_uw[2 * t][0][hslot][lk] = h1;
+                if (f % 3 == 2) s_uw[2 * t + 1][0][hslot][lk] = h1;
+                if constexpr (ZL) {
+                    if (f % 3 == 0) s_uw[2 * t][1][hslot][lk] = h2;
+                    if (f % 3 == 2) s_uw[2 * t + 1][1][hslot][lk] = h2;
                 }
+                if (f % 3 == 1) {
+                    s_v[t][0][hslot][lk] = h1;
+                    s_v[t][1][hslot][lk] = h2;
+                }
+            }
+        }
+        if constexpr (ZL) {
+            // the zero entries below level 0 and above the top of every LDS column
+            constexpr int kUwCols = 2 * NT * UWS * NCOL, kCols = kUwCols + NT * 3 * NCOL;
+            for (int i = (int)threadIdx.x; i < kCols; i += (int)blockDim.x) {
+                W* col = i < kUwCols ? &s_uw[0][0][0][0] + i * LZ : &s_v[0][0][0][0] + (i - kUwCols) * LZ;
+                col[0] = W(0);
+                col[LZ - 1] = W(0);
             }
         }
     }
@@ -390,8 +429,29 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
     // u-type F(p-1, j, k+1) is the previous step's F(p, j, k+1) of the centre,
     // the w-type F(p, j, k-1) the previous step's F(p+1, j, k-1).
     W zcar[NF];
+    if constexpr (ZL) {
+        // F(i0-1, j, k+1) of the u-type fields: that plane is not in the LDS
+        // ring, so it is loaded one level up (with that level's mask);
+        // F(i0, j, k-1) of the w-type ones from the ring
+        const unsigned voff_up = (k + 1 < g.nz) ? (unsigned)(g.h + k + 1) * (unsigned)sizeof(T) : kOutOfRange;
+        const bool up_uv = lam_uv_live(k + 1, g.nz);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) zcar[f] = f % 3 == 0 ? above(R[f][0]) : f % 3 == 2 ? below(R[f][1]) : W(0);
+        for (int f = 0; f < NF; ++f) {
+            const int t = f / 3;
+            if (f % 3 == 0) {
+                const W x = widen<T, W>(ld_raw<T, W>(column_rsrc(column(a.in[f], i0 - 1, 0), ring_bytes(f, i0 - 1)),
+                                                     voff_up));
+                zcar[f] = (f < 3 || up_uv) ? x : W(0);
+            } else if (f % 3 == 2) {
+                zcar[f] = s_uw[2 * t + 1][0][slot][lk - 1];
+            } else {
+                zcar[f] = W(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) zcar[f] = f % 3 == 0 ? above(R[f][0]) : f % 3 == 2 ? below(R[f][1]) : W(0);
+    }
 
     // LDS slots count planes from the segment start: u/w-type plane q in slot
     // (q - i0) % 2, v-type in (q - i0) % 3
@@ -405,6 +465,8 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
             const int rnew = (s + D + 2) % U;
             const int pu = (rel + s) & 1;
             const int v0 = (rel + s) % 3, v1 = (rel + s + 1) % 3, v2 = (rel + s + 2) % 3;
+            // u/w-type LDS slots of plane p and of the plane this step deposits
+            const int ur = ZL ? v0 : pu, udep = ZL ? v2 : (pu ^ 1);
 
             // prefetch plane p + D + 1
 #pragma unroll
@@ -417,7 +479,7 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
             // first use of plane p+1 (u/w-type) and p+2 (v-type deposit)
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                if (f % 3 == 1) R[f][rq1] = mask(f, widen<T, W>(R[f][rq1]));
+                if (f % 3 == 1 || ZL) R[f][rq1] = mask(f, widen<T, W>(R[f][rq1]));
                 else R[f][rq0] = mask(f, widen<T, W>(R[f][rq0]));
             }
 
@@ -431,23 +493,42 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
                     q.c = R[f][rc];
                     q.xm = R[f][rm];
                     q.xp = R[f][rq0];
-                    q.zm = f % 3 == 2 ? zcar[f] : below(q.c);
-                    q.zp = above(q.c);
+                    if constexpr (ZL) {          // z-neighbours: LDS entries lk -+ 1
+                        if (f % 3 == 0) {
+                            q.zm = s_uw[2 * t][ur][slot][lk - 1];
+                            q.zp = s_uw[2 * t][ur][slot][lk + 1];
+                        } else if (f % 3 == 1) {
+                            q.zm = s_v[t][v0][slot][lk - 1];
+                            q.zp = s_v[t][v0][slot][lk + 1];
+                        } else {
+                            q.zm = zcar[f];
+                            q.zp = s_uw[2 * t + 1][ur][slot][lk + 1];
+                        }
+                    } else {
+                        q.zm = f % 3 == 2 ? zcar[f] : below(q.c);
+                        q.zp = above(q.c);
+                    }
                     if (f % 3 == 0) {            // u-type
-                        q.ym = s_uw[2 * t][pu][slot - 1][lane];
-                        q.yp = s_uw[2 * t][pu][slot + 1][lane];
+                        q.ym = s_uw[2 * t][ur][slot - 1][lk];
+                        q.yp = s_uw[2 * t][ur][slot + 1][lk];
                         q.d1 = carry[f];         // F(p-1, j+1)
                         q.d2 = zcar[f];          // F(p-1, j, k+1)
                     } else if (f % 3 == 1) {     // v-type
                         q.ym = carry[f];         // F(p, j-1)
-                        q.yp = s_v[t][v0][slot + 1][lane];
-                        q.d1 = s_v[t][v1][slot - 1][lane];  // F(p+1, j-1)
-                        q.d2 = above(q.ym);      // F(p, j-1, k+1)
+                        q.yp = s_v[t][v0][slot + 1][lk];
+                        q.d1 = s_v[t][v1][slot - 1][lk];  // F(p+1, j-1)
+                        if constexpr (ZL) q.d2 = s_v[t][v0][slot - 1][lk + 1];
+                        else q.d2 = above(q.ym);          // F(p, j-1, k+1)
                     } else {                     // w-type
-                        q.ym = s_uw[2 * t + 1][pu][slot - 1][lane];
-                        q.yp = s_uw[2 * t + 1][pu][slot + 1][lane];
-                        q.d1 = below(q.xp);      // F(p+1, j, k-1)
-                        q.d2 = below(q.yp);      // F(p, j+1, k-1)
+                        q.ym = s_uw[2 * t + 1][ur][slot - 1][lk];
+                        q.yp = s_uw[2 * t + 1][ur][slot + 1][lk];
+                        if constexpr (ZL) {
+                            q.d1 = s_uw[2 * t + 1][v1][slot][lk - 1];
+                            q.d2 = s_uw[2 * t + 1][ur][slot + 1][lk - 1];
+                        } else {
+                            q.d1 = below(q.xp);  // F(p+1, j, k-1)
+                            q.d2 = below(q.yp);  // F(p, j+1, k-1)
+                        }
                     }
                 }
                 Star<C> sc[NF];  // operands in the arithmetic type
@@ -482,21 +563,23 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
                 buf_store(T(0), r, vpad);
             }
 
-            // deposit: u/w-type plane p+1, v-type plane p+2
+            // deposit: u/w-type plane p+1 (p+2 with ZL), v-type plane p+2
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const int t = f / 3;
-                if (f % 3 == 0) s_uw[2 * t][pu ^ 1][slot][lane] = R[f][rq0];
-                if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][slot][lane] = R[f][rq0];
-                if (f % 3 == 1) s_v[t][v2][slot][lane] = R[f][rq1];
+                const W uw = ZL ? R[f][rq1] : R[f][rq0];
+                if (f % 3 == 0) s_uw[2 * t][udep][slot][lk] = uw;
+                if (f % 3 == 2) s_uw[2 * t + 1][udep][slot][lk] = uw;
+                if (f % 3 == 1) s_v[t][v2][slot][lk] = R[f][rq1];
             }
             if (halo) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     const int t = f / 3;
-                    if (f % 3 == 0) s_uw[2 * t][pu ^ 1][hslot][lane] = mask(f, widen<T, W>(H[f][rq0]));
-                    if (f % 3 == 2) s_uw[2 * t + 1][pu ^ 1][hslot][lane] = mask(f, widen<T, W>(H[f][rq0]));
-                    if (f % 3 == 1) s_v[t][v2][hslot][lane] = mask(f, widen<T, W>(H[f][rq1]));
+                    const W uw = mask(f, widen<T, W>(ZL ? H[f][rq1] : H[f][rq0]));
+                    if (f % 3 == 0) s_uw[2 * t][udep][hslot][lk] = uw;
+                    if (f % 3 == 2) s_uw[2 * t + 1][udep][hslot][lk] = uw;
+                    if (f % 3 == 1) s_v[t][v2][hslot][lk] = mask(f, widen<T, W>(H[f][rq1]));
                 }
             }
             __syncthreads();
@@ -520,11 +603,11 @@ constexpr int kMinLX = 4;
 constexpr int kMaxLX = 128;
 constexpr int kSegmentCost = 5;
 
-Launch plan(const Geom& g, int TY, int lx, int slots, int order)
+Launch plan(const Geom& g, int TY, int lx, int slots, int order, int zw = 1)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
-    l.nchunk = g.nz <= NZ ? 1 : (g.nz + kChunk - 1) / kChunk;
+    l.nchunk = g.nz <= NZ * zw ? 1 : (g.nz + kChunk - 1) / kChunk;
     const long long cols = (long long)l.nstrips * l.nchunk;
     if (lx <= 0) {
         long long best = -1;
@@ -579,11 +662,29 @@ constexpr int kD[kVariants] = {2, 4, 2, 4, 2, 2, 2};
 constexpr bool kEH[kVariants] = {false, false, false, false, false, true, true};
 constexpr int kLdsCap[kVariants] = {65536, 65536, 65536, 65536, 163840, 163840, 163840};
 
-template <typename T, typename C, int NF, int TY>
+template <typename T, typename C, int NF, int TY, int ZW = 1>
 constexpr int lds_bytes()
 {
-    return (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ;
+    return ZW == 1 ? (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 2 + (NF / 3) * 3) * (TY + 2) * NZ
+                   : (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 3 + (NF / 3) * 3) * (TY + 2) * (NZ * ZW + 2);
 }
+
+// Columns of 65 to 256 levels (PW_MARCH_VARIANTS - 1, the default there):
+// ZW = 2 or 4 wavefronts per column, edge waves, D = 2, 16 wavefronts per
+// workgroup for the forward and 8 for the six-field kernels (whose
+// registers allow 8 per compute unit).  At 2048 x 2048 x 128 FP64 the
+// forward takes 4.8 ms and the fused pass 10.1 ms (67% and 64% of 8 TB/s),
+// against 7.8 and 17.0 ms for the best z-chunked variant; at 256 levels 9.6
+// and 21.3 ms against 15.9 and 32.6 ms.
+constexpr int kTallVariant = 7;
+template <int NF, int ZW>
+constexpr int tall_ty()
+{
+    return (NF == 6 ? 8 : 16) / ZW;
+}
+static_assert(lds_bytes<double, double, 6, tall_ty<6, 4>(), 4>() <= 163840, "LDS of one compute unit");
+static_assert(lds_bytes<double, double, 3, tall_ty<3, 4>(), 4>() <= 163840, "LDS of one compute unit");
+static_assert(lds_bytes<double, double, 6, tall_ty<6, 2>(), 2>() <= 163840, "LDS of one compute unit");
 
 // The LDS ring is static shared memory (no dynamic LDS is ever requested),
 // so the compiler sizes each instantiation's group segment; the caps keep it
@@ -614,6 +715,25 @@ void go(const MarchArgs<T, NF>& m, const Geom& g, int lx, int order, hipStream_t
     } else {
         go<T, C, NF, WS, WG, 0, UPD>(m, g, lx, order, s);
     }
+}
+
+template <typename T, typename C, int NF, bool WS, bool WG, int UPD, int ZW>
+void go_tall(const MarchArgs<T, NF>& m, const Geom& g, int lx, int order, hipStream_t s)
+{
+    constexpr int TY = tall_ty<NF, ZW>();
+    constexpr int threads = 64 * TY * ZW;
+    const auto kernel = march_kernel<T, C, NF, WS, WG, TY, 2, true, UPD, ZW>;
+    static const int per_cu = [&] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1) {
+            (void)hipGetLastError();
+            n = 1;
+        }
+        return n;
+    }();
+    const Launch l = plan(g, TY, lx, per_cu * compute_units(), order, ZW);
+    hipLaunchKernelGGL(kernel, dim3(l.grid), dim3(threads), 0, s, m, g, l.LX, l.nstrips, l.nchunk, l.nblocks,
+                       l.group);
 }
 
 // Default variant and block order per type pair, field count, output set
@@ -691,6 +811,17 @@ int default_order()
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t s)
 {
+    if (g.nz > NZ && g.nz <= 4 * NZ && (t.variant < 0 || t.variant == kTallVariant)) {
+        // natural order for the two-wavefront forward (3-7% faster at 100 and
+        // 128 levels), XCD ranges for the rest (natural is up to 8% slower for
+        // the six-field kernels at 200 and 256 levels)
+        const int order = t.order >= 0 ? t.order : (NF == 3 && g.nz <= 2 * NZ) ? 1 : 0;
+        if (g.nz <= 2 * NZ)
+            go_tall<T, C, NF, WS, WG, UPD, 2>(m, g, t.lx, order, s);
+        else
+            go_tall<T, C, NF, WS, WG, UPD, 4>(m, g, t.lx, order, s);
+        return;
+    }
     const bool small = edge16_natural<T, C, NF, WS, UPD>() && cache_resident<T>(g);
     const int v = (t.variant >= 0 && t.variant < kVariants) ? t.variant
                 : small ? 5 : default_variant<T, C, NF, WS, UPD>();

@@ -23,7 +23,7 @@ PW_F64, PW_F32, PW_F32_F64, PW_F16, PW_BF16 = 0, 1, 2, 3, 4
 KERNELS = {"auto": 0, "direct": 1, "march": 2}
 # tuning knobs of the calling thread (pw_set_tuning)
 TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT, TUNE_BLOCK_ORDER = 0, 1, 2, 3, 4
-MARCH_VARIANTS = 7
+MARCH_VARIANTS = 8
 COPY_OUT = {"runtime": 0, "kernel": 1}
 ORDERS = {"default": -1, "xcd": 0, "natural": 1}   # or an int G: groups of G strips per XCD
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",

@@ -14,7 +14,7 @@ from paper_2010_01545_amd import inputs
 
 H = inputs.HALO
 # every x-marching variant the library builds (PW_TUNE_MARCH_VARIANT values)
-MARCH_VARIANTS = list(range(7))
+MARCH_VARIANTS = list(range(8))
 
 
 def log(msg):
