@@ -122,7 +122,7 @@ enum {
                                   one wavefront per column and cut columns of
                                   more than 64 levels into z-chunks; variant
                                   PW_MARCH_VARIANTS-1 holds a column of 65..256
-                                  levels in 2 or 4 wavefronts of one workgroup
+                                  levels in 2 to 4 wavefronts of one workgroup
                                   (the default for such columns; for other
                                   columns it selects the default variant) */
     PW_TUNE_MARCH_LX = 2,      /* x-planes per marching workgroup, or 0 to choose

@@ -17,7 +17,7 @@
 //     ring.  With TY a multiple of 4 the arithmetic spreads evenly over the
 //     four SIMDs of a compute unit, which pays where the arithmetic, not HBM,
 //     sets the pace.
-// Columns of 65 to 256 levels are held by ZW = 2 or 4 wavefronts of one
+// Columns of 65 to 256 levels are held by ZW = 2, 3 or 4 wavefronts of one
 // workgroup, wave z holding levels 64 z .. 64 z + 63.  Their z-neighbours
 // come from the LDS ring instead of wavefront shifts: it then holds whole
 // columns, with a zero entry below level 0 and above the top, and keeps
@@ -238,14 +238,14 @@ struct MarchArgs {
 // b streamed through the register ring like the fields (b may be the output
 // itself: each element is read planes before the same wave writes it); 2 the
 // same with b = (u, v, w), whose centre values are already in the ring.
-// ZW: wavefronts per column (1, or 2 or 4 for columns of up to 128 or 256
-// levels, whose z-neighbours then come from the LDS ring).
+// ZW: wavefronts per column (1, or 2, 3 or 4 for columns of up to 128, 192
+// or 256 levels, whose z-neighbours then come from the LDS ring).
 template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, bool EH, int UPD = 0, int ZW = 1>
 __global__ void __launch_bounds__(64 * (EH ? TY : TY + 2) * ZW)
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks, int group)
 {
     static_assert(D >= 2, "v-type fields deposit plane p+2 from the register ring");
-    static_assert(ZW == 1 || ZW == 2 || ZW == 4, "one, two or four wavefronts per column");
+    static_assert(ZW >= 1 && ZW <= 4, "one to four wavefronts per column");
     static_assert(!EH || TY >= 2, "the two halo columns belong to different edge waves");
     static_assert(UPD == 0 || (NF == 3 && WS && !WG), "the update form is a forward-only epilogue");
     constexpr int NCOL = TY + 2;    // LDS slots
@@ -670,9 +670,9 @@ constexpr int lds_bytes()
 }
 
 // Columns of 65 to 256 levels (PW_MARCH_VARIANTS - 1, the default there):
-// ZW = 2 or 4 wavefronts per column, edge waves, D = 2, 16 wavefronts per
-// workgroup for the forward and 8 for the six-field kernels (whose
-// registers allow 8 per compute unit).  At 2048 x 2048 x 128 FP64 the
+// ZW = 2, 3 or 4 wavefronts per column, edge waves, D = 2, 16 (15 with
+// ZW = 3) wavefronts per workgroup for the forward and 8 (6) for the
+// six-field kernels (whose registers allow 8 per compute unit).  At 2048 x 2048 x 128 FP64 the
 // forward takes 4.8 ms and the fused pass 10.1 ms (67% and 64% of 8 TB/s),
 // against 7.8 and 17.0 ms for the best z-chunked variant; at 256 levels 9.6
 // and 21.3 ms against 15.9 and 32.6 ms.
@@ -685,6 +685,8 @@ constexpr int tall_ty()
 static_assert(lds_bytes<double, double, 6, tall_ty<6, 4>(), 4>() <= 163840, "LDS of one compute unit");
 static_assert(lds_bytes<double, double, 3, tall_ty<3, 4>(), 4>() <= 163840, "LDS of one compute unit");
 static_assert(lds_bytes<double, double, 6, tall_ty<6, 2>(), 2>() <= 163840, "LDS of one compute unit");
+static_assert(lds_bytes<double, double, 6, tall_ty<6, 3>(), 3>() <= 163840, "LDS of one compute unit");
+static_assert(lds_bytes<double, double, 3, tall_ty<3, 3>(), 3>() <= 163840, "LDS of one compute unit");
 
 // The LDS ring is static shared memory (no dynamic LDS is ever requested),
 // so the compiler sizes each instantiation's group segment; the caps keep it
@@ -818,6 +820,8 @@ void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t
         const int order = t.order >= 0 ? t.order : (NF == 3 && g.nz <= 2 * NZ) ? 1 : 0;
         if (g.nz <= 2 * NZ)
             go_tall<T, C, NF, WS, WG, UPD, 2>(m, g, t.lx, order, s);
+        else if (g.nz <= 3 * NZ)
+            go_tall<T, C, NF, WS, WG, UPD, 3>(m, g, t.lx, order, s);
         else
             go_tall<T, C, NF, WS, WG, UPD, 4>(m, g, t.lx, order, s);
         return;

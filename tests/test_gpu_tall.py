@@ -2,7 +2,8 @@
 by two or four wavefronts of one workgroup whose z-neighbours come from the
 LDS ring: bit for bit against the direct kernel (which is tested against the
 oracle in test_gpu_parity), forward, adjoint, fused pass and both update
-forms, for every storage type, at heights on both sides of 128 and at 256,
+forms, for every storage type, at heights on both sides of 128 and 192 and
+at 256,
 with several x-segments, narrow last strips, three block orders and halo
 widths 1 to 3; and once against the oracle itself."""
 import numpy as np
@@ -61,11 +62,11 @@ def _same(a, b):
     return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(np.nan_to_num(a), np.nan_to_num(b))
 
 
-@pytest.mark.parametrize("nz", [65, 100, 128, 129, 200, 256])
+@pytest.mark.parametrize("nz", [65, 100, 128, 129, 150, 192, 193, 256])
 @pytest.mark.parametrize("kind", list(KINDS))
 def test_tall_columns_match_direct(pw, kind, nz):
     """Default kernel selection (two wavefronts per column up to 128 levels,
-    four up to 256) against the direct kernel, with x-segments of 5 planes
+    three up to 192, four up to 256) against the direct kernel, with x-segments of 5 planes
     and ny = 11, which leaves a last strip narrower than the strip width."""
     dtype, compute = KINDS[kind]
     nx, ny, h, seed = 13, 11, 2, 300 + nz
@@ -79,7 +80,7 @@ def test_tall_columns_match_direct(pw, kind, nz):
 
 
 @pytest.mark.parametrize("order", ["xcd", "natural", 2])
-@pytest.mark.parametrize("shape", [(9, 7, 100, 1), (6, 5, 256, 1), (7, 9, 150, 3), (5, 3, 70, 3)],
+@pytest.mark.parametrize("shape", [(9, 7, 100, 1), (6, 5, 256, 1), (7, 9, 150, 3), (5, 3, 70, 3), (6, 11, 180, 2)],
                          ids=lambda s: "x".join(map(str, s[:3])) + "h%d" % s[3])
 def test_tall_orders_and_halos(pw, shape, order):
     """Block orders and halo widths 1 and 3 (the edge waves address their
