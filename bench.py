@@ -351,20 +351,24 @@ def offload_measure(pw, torch, reps=4, chunk=64):
         return ev[0].elapsed_time(ev[1]) / n
 
     run = lambda: pw.fwd_host(*host_in, g.t1, g.t2, g.tcx, g.tcy, h, *host_out, chunk, ws)
-    # copy-out modes: the runtime's copies (the default) and the library's
-    # copy kernel; both warmed, then timed call by call in alternation so
-    # that neither profits from the other's warm-up
-    calls = {"runtime": [], "kernel": []}
-    for mode in calls:
-        with pw.tuning(copy_out=mode):
-            run()
-        torch.cuda.synchronize()
+    # copy-out modes: the runtime's copies, the library's copy kernel, direct
+    # writes by the advection kernel, and the automatic choice among them (the
+    # default; it learns from every call's time); all warmed, then timed call
+    # by call in alternation so that none profits from another's warm-up
+    calls = {"runtime": [], "kernel": [], "direct": [], "auto": []}
+    for _ in range(2):      # (the first call of each mode carries one-time costs)
+        for mode in calls:
+            with pw.tuning(copy_out=mode):
+                run()
+            torch.cuda.synchronize()
     for _ in range(reps):
         for mode in calls:
             with pw.tuning(copy_out=mode):
                 calls[mode].append(timed(run, 1))
     med = lambda v: sorted(v)[len(v) // 2]
-    t_off, t_off_k = med(calls["runtime"]), med(calls["kernel"])
+    by_mode = {m: med(v) for m, v in calls.items()}
+    default_mode = {v: k for k, v in pw.COPY_OUT.items()}[pw.get_tuning(pw.TUNE_COPY_OUT)]
+    t_off = by_mode[default_mode]
     t_h2d = timed(lambda: [d.copy_(hsrc, non_blocking=True) for d, hsrc in zip(g.f, host_in)], reps)
     t_d2h = timed(lambda: [o.copy_(d, non_blocking=True) for o, d in zip(host_out, g.s)], reps)
     t_k = timed(lambda: g.launch(pw, "fwd"), reps)
@@ -375,7 +379,8 @@ def offload_measure(pw, torch, reps=4, chunk=64):
         "cells": cells,
         "gcells_per_s_incl_transfers": cells / (t_off * 1e-3) / 1e9,
         "ms_pipelined": t_off,
-        "ms_pipelined_copy_kernel_out": t_off_k,
+        "copy_out_default": default_mode,
+        "ms_pipelined_by_copy_out": by_mode,
         "ms_per_call": {k: [round(x, 2) for x in v] for k, v in calls.items()},
         "ms_copy_in_alone": t_h2d, "ms_copy_out_alone": t_d2h, "ms_kernel_alone": t_k,
         "copy_in_GBps": nbytes / (t_h2d * 1e-3) / 1e9, "copy_out_GBps": nbytes / (t_d2h * 1e-3) / 1e9,
@@ -610,10 +615,11 @@ def main():
     if not args.no_offload:
         log("bench: host-resident offload at 4096x1024x64")
         out["offload"] = offload_measure(pw, torch)
-        log("bench: offload %.1f ms pipelined, %.1f with the copy kernel out (in %.1f, kernel %.1f, out %.1f)" % (
-            out["offload"]["ms_pipelined"], out["offload"]["ms_pipelined_copy_kernel_out"],
-            out["offload"]["ms_copy_in_alone"],
-            out["offload"]["ms_kernel_alone"], out["offload"]["ms_copy_out_alone"]))
+        o = out["offload"]
+        log("bench: offload %.1f ms pipelined (%s); by copy-out mode %s (in %.1f, kernel %.1f, out %.1f)" % (
+            o["ms_pipelined"], o["copy_out_default"],
+            ", ".join("%s %.1f" % kv for kv in o["ms_pipelined_by_copy_out"].items()),
+            o["ms_copy_in_alone"], o["ms_kernel_alone"], o["ms_copy_out_alone"]))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, seed)

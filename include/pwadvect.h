@@ -32,9 +32,9 @@
  * the caller, except the host field arrays of pw_advect_fwd_host.  The library
  * allocates no memory and reads no environment variables.  The state it keeps
  * is per thread (the tuning knobs of pw_set_tuning and the last error text)
- * or created once per device (two copy streams and a few events, from the
- * first pw_advect_fwd_host call on that device until the process ends), so
- * every call is thread-safe.
+ * or created once per device (two copy streams, a few events and the recent
+ * times of pw_advect_fwd_host calls per copy-out mode, from the first such
+ * call on that device until the process ends), so every call is thread-safe.
  *
  * ---------------------------------------------------------------- semantics
  * Levels follow Listing 1: Fortran k = 2..z_size is interior k = 1..nz-1.
@@ -128,7 +128,7 @@ enum {
     PW_TUNE_MARCH_LX = 2,      /* x-planes per marching workgroup, or 0 to choose
                                   from the grid [0] */
     PW_TUNE_COPY_OUT = 3,      /* how pw_advect_fwd_host returns the source terms,
-                                  PW_COPY_OUT_* [PW_COPY_OUT_RUNTIME] */
+                                  PW_COPY_OUT_* [PW_COPY_OUT_AUTO] */
     PW_TUNE_BLOCK_ORDER = 4    /* order of the x-marching workgroups over the
                                   strips: PW_ORDER_XCD, or G in
                                   1..PW_ORDER_MAX_GROUP for groups of G
@@ -145,9 +145,24 @@ enum {
 enum { PW_MARCH_VARIANTS = 8 };
 enum {
     PW_COPY_OUT_RUNTIME = 0, /* the HIP runtime's device-to-host copies */
-    PW_COPY_OUT_KERNEL = 1   /* a copy kernel writing pinned host outputs that are
+    PW_COPY_OUT_KERNEL = 1,  /* a copy kernel writing pinned host outputs that are
                                 mapped into the device's address space (other
                                 outputs still use the runtime's copies) */
+    PW_COPY_OUT_DIRECT = 2,  /* the advection kernel itself writes pinned host
+                                outputs mapped into the device's address space
+                                (no copy out: the kernel's stores cross PCIe
+                                while the next slab comes in; other outputs, and
+                                outputs whose planes are not 16-byte aligned for
+                                the x-marching kernels, use the runtime's
+                                copies) */
+    PW_COPY_OUT_AUTO = 3     /* per device, the mode of the three that the
+                                outputs allow and that has been fastest: every
+                                call is timed with two events on `stream`, and
+                                a later call reads the times of the calls that
+                                have finished (without waiting), trying each
+                                allowed mode first and the others again every
+                                eighth call.  Only the speed depends on it: the
+                                results are identical in every mode. */
 };
 
 /*
@@ -230,9 +245,10 @@ int pw_advect_fwd_update(const void *u, const void *v, const void *w,
  * `stream`; the copies use two streams the library creates once per device and
  * keeps until the process ends (default priority).  Inputs go in through the
  * runtime's host-to-device copies, outputs come back through the runtime's
- * device-to-host copies unless the calling thread set PW_TUNE_COPY_OUT to
- * PW_COPY_OUT_KERNEL (then pinned outputs mapped into the device's address
- * space are written by a copy kernel of the library).  Concurrent calls are
+ * device-to-host copies, a copy kernel of the library or the advection kernel
+ * itself writing pinned outputs mapped into the device's address space, as
+ * PW_TUNE_COPY_OUT selects (by default the fastest of these measured on the
+ * device, PW_COPY_OUT_AUTO).  Concurrent calls are
  * serialized while they are queued.  Results are identical to pw_advect_fwd on
  * the same data.  Errors as for pw_advect_fwd; PW_ERR_ARG if a field array is
  * device memory, PW_ERR_SIZE if the workspace is too small.

@@ -21,7 +21,7 @@ struct Tuning {
     int kernel = PW_KERNEL_AUTO;
     int variant = -1;                 // < 0: default variant
     int lx = 0;                       // 0: segment length from the grid
-    int copy_out = PW_COPY_OUT_RUNTIME;
+    int copy_out = PW_COPY_OUT_AUTO;
     int order = -1;                   // < 0: default block order, 0: XCD ranges, G: groups of G
 };
 thread_local Tuning g_tune;
@@ -373,20 +373,29 @@ int do_fwd_host(const char* name, const void* u, const void* v, const void* w, c
     const Arr ws[1] = {{workspace, need, 16, "workspace"}};
     const int kern = with_types(dtype, [&](auto t, auto) { return resolve_kernel<decltype(t)>(sg, ws, 1); });
     if (kern < 0) return fail(PW_ERR_UNSUPPORTED, "x-marching kernel needs halo <= 32 and columns under 1 GiB");
-    // outputs go back through the runtime's copies unless the thread asked
-    // for the copy kernel and they are pinned host memory mapped into the
-    // device's address space
+    // outputs go back through the runtime's copies unless the copy-out mode
+    // (the thread's, or the automatic choice) is the copy kernel or direct
+    // writes and they are pinned host memory mapped into the device's address
+    // space; direct writes from the x-marching kernels also need every slab's
+    // first plane 16-byte aligned
     void* od[3] = {nullptr, nullptr, nullptr};
-    bool mapped = g_tune.copy_out == PW_COPY_OUT_KERNEL;
+    const int mode = g_tune.copy_out;
+    bool mapped = mode != PW_COPY_OUT_RUNTIME;
     for (int f = 0; f < 3 && mapped; ++f) mapped = (od[f] = mapped_host(out[f].p, bytes)) != nullptr;
     const char* what = "";
     const bool march = kern == PW_KERNEL_MARCH;
+    bool direct_ok = mapped;
+    if (direct_ok && march) {
+        const size_t plane_bytes = (size_t)g.sx * es;
+        for (int f = 0; f < 3; ++f)
+            if ((uintptr_t)od[f] % 16 || plane_bytes % 16) direct_ok = false;
+    }
     const int e = with_types(dtype, [&](auto t, auto c) {
         using T = decltype(t);
         T* const o[3] = {(T*)od[0], (T*)od[1], (T*)od[2]};
         return offload_fwd<T, decltype(c)>((const T*)u, (const T*)v, (const T*)w, tzc1, tzc2, tcx, tcy, g, (T*)su,
-                                           (T*)sv, (T*)sw, mapped ? o : nullptr, chunk, workspace, march,
-                                           use_static, march_tune(), (hipStream_t)stream, &what);
+                                           (T*)sv, (T*)sw, mapped ? o : nullptr, direct_ok, mode, chunk, workspace,
+                                           march, use_static, march_tune(), (hipStream_t)stream, &what);
     });
     if (e) return fail(PW_ERR_HIP, "%s: %s: %s", name, what, hipGetErrorString((hipError_t)e));
     return launched(name);
@@ -595,7 +604,8 @@ int pw_set_tuning(int knob, int value)
         g_tune.lx = value;
         break;
     case PW_TUNE_COPY_OUT:
-        if (value != PW_COPY_OUT_RUNTIME && value != PW_COPY_OUT_KERNEL)
+        if (value != PW_COPY_OUT_RUNTIME && value != PW_COPY_OUT_KERNEL && value != PW_COPY_OUT_DIRECT &&
+            value != PW_COPY_OUT_AUTO)
             return fail(PW_ERR_ARG, "unknown copy-out mode %d", value);
         g_tune.copy_out = value;
         break;

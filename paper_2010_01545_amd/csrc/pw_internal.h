@@ -72,16 +72,18 @@ void launch_stream_copy(const void* const* src, void* const* dst, int n, size_t 
 
 // Host-resident fields: chunked, pipelined forward (pw_offload.hip).  out_dev
 // holds the device addresses of su, sv, sw when they are mapped pinned host
-// memory and the copy kernel was asked for (it then writes them), else
-// nullptr (runtime copies).
+// memory, else nullptr; direct_ok: the slab kernels may write them directly;
+// copy_out: PW_COPY_OUT_* (a mode the outputs do not allow falls back to
+// the runtime's copies).
 // With after_previous the call's copies and kernels start after the last copy
 // out of the offload call queued before it on the device (its buffers may be
 // the same).
 size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es);
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
-                const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
-                bool after_previous, MarchTune tune, hipStream_t stream, const char** what);
+                const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, bool direct_ok, int copy_out, int chunk,
+                void* workspace, bool use_march, bool after_previous, MarchTune tune, hipStream_t stream,
+                const char** what);
 
 // Static scratch of pw_advect_fwd_host_static (pw_offload.hip): its size and
 // the current device's address of it (looked up once per device).

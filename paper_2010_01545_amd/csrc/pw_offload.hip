@@ -19,17 +19,27 @@
 // The internal streams and events are created once per device (default
 // priority) and kept for the life of the process.
 //
-// Copies out.  By default the runtime's 2-D copy writes each slab's rows
-// back.  When the caller's thread asks for the copy kernel and the output
-// arrays are pinned host memory mapped into the device's address space
-// (out_dev holds their device addresses), a copy kernel on the copy-out
-// stream writes them instead, leaving the copy engines to the inputs.  With
-// both directions on copy engines the runtime now and then puts them on one
-// engine and the two transfers serialise, but on average the runtime's copies
-// were as fast or faster (measured at 4096 x 1024 x 64 FP64: 147-151 ms per
-// call, or about 250 ms in roughly one call of five, against 165-171 ms every
-// call with the copy kernel; on another kind of machine 211 ms against
-// 260-274 ms).
+// Copies out, three ways.  The runtime's 2-D copy writes each slab's rows
+// back from the copy-out stream.  For output arrays in pinned host memory
+// mapped into the device's address space (out_dev holds their device
+// addresses), a copy kernel on the copy-out stream can write them instead,
+// leaving the copy engines to the inputs; or the slab kernels store straight
+// into the mapped host arrays (the slab's planes at their place in the host
+// array: the slab geometry has the host array's plane size), so nothing is
+// copied out and the kernel's stores cross PCIe while the next slab's inputs
+// come in.
+//
+// Which is fastest depends on the machine: with both directions on copy
+// engines the runtime sometimes serialises them on one engine (on one kind
+// of machine 148-150 ms per call at 4096 x 1024 x 64 FP64, now and then 258
+// ms, against 167 ms with the copy kernel and 170 ms with direct writes; on
+// another 214 ms, or 457 ms in three calls of four, against 272 ms with the
+// copy kernel).  In the automatic mode (the default) every call is timed
+// with two events on the caller's stream; a later call reads the times of
+// the calls that have finished (hipEventQuery: it never waits) and takes the
+// mode with the lowest recent time per byte, after first trying each mode
+// the call allows and trying the others again every eighth call.
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/pwadvect.h"
@@ -88,11 +98,33 @@ void copy_rows(const void* src, void* dst, size_t pitch, size_t row, int rows, h
     }
 }
 
+constexpr int kModes = 3;       // PW_COPY_OUT_RUNTIME, _KERNEL, _DIRECT
+constexpr int kTimed = 8;       // calls whose times may be outstanding
+constexpr int kRetryEvery = 8;  // automatic mode: retry the other modes every this many calls
+constexpr int kSamples = 3;     // times kept per mode (one slow call among three does not move the choice)
+
+struct CallTimer {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int mode = 0;
+    double gbytes = 0.0;
+    bool live = false;
+};
+
 struct DeviceQueues {
     bool ready = false;
     hipStream_t h2d = nullptr, d2h = nullptr;
     hipEvent_t start = nullptr, done_in[kBuffers] = {}, done_kernel[kBuffers] = {}, done_out[kBuffers] = {},
                end_out = nullptr;
+    // automatic copy-out choice: the last kSamples times of each mode in ms
+    // per GB, their cost (the median of three, the lower of two; < 0: no
+    // sample yet), the call count at its last sample, and the timers in flight
+    double samples[kModes][kSamples] = {};
+    int nsamples[kModes] = {0, 0, 0};
+    double cost[kModes] = {-1.0, -1.0, -1.0};
+    long long sampled_at[kModes] = {-1, -1, -1};
+    long long calls = 0;
+    CallTimer timers[kTimed];
+    int next_timer = 0;
 };
 
 std::mutex g_queues_mutex;
@@ -118,10 +150,63 @@ hipError_t queues_for_current_device(DeviceQueues** out)
             if ((e = hipEventCreateWithFlags(&q.done_kernel[b], ev)) != hipSuccess) return e;
             if ((e = hipEventCreateWithFlags(&q.done_out[b], ev)) != hipSuccess) return e;
         }
+        for (int t = 0; t < kTimed; ++t) {   // timing events
+            if ((e = hipEventCreateWithFlags(&q.timers[t].t0, hipEventDefault)) != hipSuccess) return e;
+            if ((e = hipEventCreateWithFlags(&q.timers[t].t1, hipEventDefault)) != hipSuccess) return e;
+        }
         q.ready = true;
     }
     *out = &q;
     return hipSuccess;
+}
+
+// Fold the times of finished calls into the per-mode costs (never waits).
+void harvest_timers(DeviceQueues* q)
+{
+    for (CallTimer& t : q->timers) {
+        if (!t.live) continue;
+        const hipError_t e = hipEventQuery(t.t1);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();
+            continue;
+        }
+        float ms = 0.0f;
+        if (e == hipSuccess && hipEventElapsedTime(&ms, t.t0, t.t1) == hipSuccess && t.gbytes > 0.0) {
+            const int m = t.mode;
+            double* s = q->samples[m];
+            for (int i = kSamples - 1; i > 0; --i) s[i] = s[i - 1];
+            s[0] = (double)ms / t.gbytes;
+            if (q->nsamples[m] < kSamples) ++q->nsamples[m];
+            const int n = q->nsamples[m];
+            const double lo = std::min(s[0], s[1]), hi = std::max(s[0], s[1]);
+            q->cost[m] = n == 1 ? s[0] : n == 2 ? lo : std::max(lo, std::min(hi, s[2]));
+            q->sampled_at[m] = q->calls;
+        }
+        (void)hipGetLastError();
+        t.live = false;
+    }
+}
+
+// Copy-out mode for an automatic-mode call: a mode the call allows that has
+// no time yet (and none in flight), else every kRetryEvery-th call the
+// allowed mode sampled longest ago, else the lowest recent cost.  Without
+// exploring (a call being captured into a graph): the lowest cost known.
+int choose_copy_out(DeviceQueues* q, const bool allowed[kModes], bool explore)
+{
+    bool pending[kModes] = {false, false, false};
+    for (const CallTimer& t : q->timers)
+        if (t.live) pending[t.mode] = true;
+    for (int m = 0; m < kModes && explore; ++m)
+        if (allowed[m] && q->cost[m] < 0.0 && !pending[m]) return m;
+    int best = PW_COPY_OUT_RUNTIME;
+    if (explore && q->calls % kRetryEvery == 0) {
+        for (int m = 0; m < kModes; ++m)
+            if (allowed[m] && q->sampled_at[m] < q->sampled_at[best]) best = m;
+        return best;
+    }
+    for (int m = 0; m < kModes; ++m)
+        if (allowed[m] && q->cost[m] >= 0.0 && (q->cost[best] < 0.0 || q->cost[m] < q->cost[best])) best = m;
+    return best;
 }
 
 }  // namespace
@@ -171,8 +256,9 @@ size_t offload_workspace_bytes(const Geom& g, int chunk, size_t es)
 
 template <typename T, typename C>
 int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const double* tzc2, double tcx, double tcy,
-                const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, int chunk, void* workspace, bool use_march,
-                bool after_previous, MarchTune tune, hipStream_t stream, const char** what)
+                const Geom& g, T* su, T* sv, T* sw, T* const* out_dev, bool direct_ok, int copy_out, int chunk,
+                void* workspace, bool use_march, bool after_previous, MarchTune tune, hipStream_t stream,
+                const char** what)
 {
     DeviceQueues* q = nullptr;
     hipError_t e = queues_for_current_device(&q);
@@ -183,12 +269,30 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
     // one enqueue at a time per process: the internal streams and events are
     // shared, and each wait captures the event's latest record when it is queued
     std::lock_guard<std::mutex> lock(g_enqueue_mutex);
+    // a call captured into a graph records and queries no timing events
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool timed = hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone;
+    (void)hipGetLastError();
+    if (timed) harvest_timers(q);
+    const bool allowed[kModes] = {true, out_dev != nullptr, out_dev != nullptr && direct_ok};
+    int mode = copy_out == PW_COPY_OUT_AUTO ? choose_copy_out(q, allowed, timed)
+             : (copy_out >= 0 && copy_out < kModes && allowed[copy_out]) ? copy_out : PW_COPY_OUT_RUNTIME;
+    if (timed) ++q->calls;
+    const bool direct = mode == PW_COPY_OUT_DIRECT;
+    if (mode == PW_COPY_OUT_RUNTIME) out_dev = nullptr;
+    CallTimer* timer = nullptr;
+    if (timed) {
+        timer = &q->timers[q->next_timer];
+        q->next_timer = (q->next_timer + 1) % kTimed;
+        timer->live = false;   // (a time still in flight when its slot is reused is dropped)
+    }
     // a call whose buffers another call may still use (the static scratch)
     // starts after the last copy out of the call queued before it
     if (after_previous) {
         if ((e = hipStreamWaitEvent(q->h2d, q->end_out, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
         if ((e = hipStreamWaitEvent(stream, q->end_out, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
     }
+    if (timer && (e = hipEventRecord(timer->t0, stream)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
     const size_t plane = (size_t)g.sx;                       // elements per storage plane
     const size_t slab = (size_t)(chunk + 2 * g.h) * plane;   // elements per slab array
     T* base = (T*)workspace;
@@ -225,11 +329,15 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
         if ((e = hipEventRecord(q->done_in[b], q->h2d)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
         // kernel on the slab
         if ((e = hipStreamWaitEvent(stream, q->done_in[b], 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
-        if (k >= kBuffers && (e = hipStreamWaitEvent(stream, q->done_out[b], 0)) != hipSuccess) {
+        if (!direct && k >= kBuffers && (e = hipStreamWaitEvent(stream, q->done_out[b], 0)) != hipSuccess) {
             *what = "hipStreamWaitEvent";
             return (int)e;
         }
-        FwdArgs<T> a{buf(b, 0), buf(b, 1), buf(b, 2), tzc1, tzc2, tcx, tcy, buf(b, 3), buf(b, 4), buf(b, 5)};
+        // direct writes: plane p of the slab is plane i0 + p of the host array
+        T* const o0 = direct ? out_dev[0] + (size_t)i0 * plane : buf(b, 3);
+        T* const o1 = direct ? out_dev[1] + (size_t)i0 * plane : buf(b, 4);
+        T* const o2 = direct ? out_dev[2] + (size_t)i0 * plane : buf(b, 5);
+        FwdArgs<T> a{buf(b, 0), buf(b, 1), buf(b, 2), tzc1, tzc2, tcx, tcy, o0, o1, o2};
         (void)hipGetLastError();
         if (use_march)
             launch_fwd_march<T, C>(a, sg, tune, stream);
@@ -237,6 +345,7 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
             launch_fwd_direct<T, C>(a, sg, stream);
         if ((e = hipGetLastError()) != hipSuccess) { *what = "kernel launch"; return (int)e; }
         if ((e = hipEventRecord(q->done_kernel[b], stream)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+        if (direct) continue;
         // outputs: interior columns of the slab's c interior planes
         if ((e = hipStreamWaitEvent(q->d2h, q->done_kernel[b], 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
         for (int f = 0; f < 3; ++f) {
@@ -252,16 +361,26 @@ int offload_fwd(const T* u, const T* v, const T* w, const double* tzc1, const do
         }
         if ((e = hipEventRecord(q->done_out[b], q->d2h)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
     }
-    // later work on the caller's stream sees every copy back
-    if ((e = hipEventRecord(q->end_out, q->d2h)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+    // later work on the caller's stream sees every copy back (with direct
+    // writes the last kernel is the call's last step)
+    if ((e = hipEventRecord(q->end_out, direct ? stream : q->d2h)) != hipSuccess) {
+        *what = "hipEventRecord";
+        return (int)e;
+    }
     if ((e = hipStreamWaitEvent(stream, q->end_out, 0)) != hipSuccess) { *what = "hipStreamWaitEvent"; return (int)e; }
+    if (timer) {
+        if ((e = hipEventRecord(timer->t1, stream)) != hipSuccess) { *what = "hipEventRecord"; return (int)e; }
+        timer->mode = mode;
+        timer->gbytes = (double)((size_t)2 * 3 * (size_t)g.Sx * plane * sizeof(T)) * 1e-9;
+        timer->live = true;
+    }
     return 0;
 }
 
 #define PW_OFFLOAD_INSTANCE(T, C)                                                                            \
     template int offload_fwd<T, C>(const T*, const T*, const T*, const double*, const double*, double, double, \
-                                   const Geom&, T*, T*, T*, T* const*, int, void*, bool, bool, MarchTune,      \
-                                   hipStream_t, const char**);
+                                   const Geom&, T*, T*, T*, T* const*, bool, int, int, void*, bool, bool,     \
+                                   MarchTune, hipStream_t, const char**);
 PW_OFFLOAD_INSTANCE(double, double)
 PW_OFFLOAD_INSTANCE(float, float)
 PW_OFFLOAD_INSTANCE(float, double)

@@ -24,7 +24,7 @@ KERNELS = {"auto": 0, "direct": 1, "march": 2}
 # tuning knobs of the calling thread (pw_set_tuning)
 TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT, TUNE_BLOCK_ORDER = 0, 1, 2, 3, 4
 MARCH_VARIANTS = 8
-COPY_OUT = {"runtime": 0, "kernel": 1}
+COPY_OUT = {"runtime": 0, "kernel": 1, "direct": 2, "auto": 3}
 ORDERS = {"default": -1, "xcd": 0, "natural": 1}   # or an int G: groups of G strips per XCD
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
           -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
@@ -327,8 +327,8 @@ def set_tuning(knob, value):
 class tuning:
     """Context manager: set tuning knobs of the calling thread for a block
     and restore them afterwards, e.g. ``with pw.tuning(variant=3, lx=7):``.
-    Keywords: kernel ('auto', 'direct', 'march'), variant (-1..6), lx (planes
-    per marching workgroup, 0 = automatic), copy_out ('runtime', 'kernel'),
+    Keywords: kernel ('auto', 'direct', 'march'), variant (-1..7), lx (planes
+    per marching workgroup, 0 = automatic), copy_out ('runtime', 'kernel', 'direct', 'auto'),
     order ('default', 'xcd', 'natural', or an int G: groups of G neighbouring
     strips per XCD)."""
 

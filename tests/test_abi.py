@@ -196,12 +196,12 @@ def _get(lib, knob):
 
 def test_tuning_knobs_set_get_and_reject(lib):
     lib.pw_get_tuning.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    defaults = {PW_TUNE_KERNEL: 0, PW_TUNE_MARCH_VARIANT: -1, PW_TUNE_MARCH_LX: 0, PW_TUNE_COPY_OUT: 0,
+    defaults = {PW_TUNE_KERNEL: 0, PW_TUNE_MARCH_VARIANT: -1, PW_TUNE_MARCH_LX: 0, PW_TUNE_COPY_OUT: 3,
                 PW_TUNE_BLOCK_ORDER: -1}
     for knob, d in defaults.items():
         assert _get(lib, knob) == (PW_OK, d)
     for knob, good, bad in ((PW_TUNE_KERNEL, 2, 3), (PW_TUNE_MARCH_VARIANT, 7, 8),
-                            (PW_TUNE_MARCH_LX, 9, -1), (PW_TUNE_COPY_OUT, 1, 2), (PW_TUNE_BLOCK_ORDER, 16, 65537)):
+                            (PW_TUNE_MARCH_LX, 9, -1), (PW_TUNE_COPY_OUT, 2, 4), (PW_TUNE_BLOCK_ORDER, 16, 65537)):
         assert lib.pw_set_tuning(knob, good) == PW_OK
         assert _get(lib, knob) == (PW_OK, good)
         assert lib.pw_set_tuning(knob, bad) == PW_ERR_ARG

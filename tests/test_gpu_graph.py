@@ -61,3 +61,45 @@ def test_fused_step_replays_in_a_graph(pw, dtype, kernel):
                 assert np.array_equal(gi, ei), "replay %d output %d" % (r, q)
     finally:
         pw.set_kernel(prev)
+
+
+@pytest.mark.parametrize("copy_out", ["auto", "runtime", "kernel", "direct"])
+def test_static_offload_replays_in_a_graph(pw, copy_out):
+    """The allocation-free offload (pw_advect_fwd_host_static) with pinned
+    host fields, captured once and replayed: each replay matches an eager
+    call bit for bit, with the host inputs rewritten and the host outputs
+    poisoned between replays.  A captured call records and queries no timing
+    events (the automatic copy-out mode uses what it measured before)."""
+    log("graph offload %s" % copy_out)
+    fields, _, coef = host_case(13, 11, 64, 93)
+    tzc1, tzc2, tcx, tcy = coef
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    st = [oracle.pad_periodic(a, H) for a in fields]
+    host_in = [torch.from_numpy(a).pin_memory() for a in st]
+    outs = [torch.full(host_in[0].shape, float("nan"), dtype=torch.float64, pin_memory=True) for _ in range(3)]
+    chunk = 4
+    with pw.tuning(copy_out=copy_out):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):   # warm-up calls off the default stream (and timed, for "auto")
+            for _ in range(3):
+                pw.fwd_host_static(*host_in, t1, t2, tcx, tcy, H, *outs, chunk)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            pw.fwd_host_static(*host_in, t1, t2, tcx, tcy, H, *outs, chunk)
+        torch.cuda.synchronize()
+        for r in range(3):
+            for q, t in enumerate(host_in):     # new host inputs (halos stay periodic: a scaled copy)
+                t.copy_(torch.from_numpy(st[q] * (1.0 + 0.25 * r)))
+            ref = [torch.full(o.shape, float("nan"), dtype=o.dtype, pin_memory=True) for o in outs]
+            pw.fwd_host_static(*host_in, t1, t2, tcx, tcy, H, *ref, chunk)
+            torch.cuda.synchronize()
+            for t in outs:
+                t.fill_(float("nan"))
+            graph.replay()
+            torch.cuda.synchronize()
+            for q, (g, e) in enumerate(zip(outs, ref)):
+                assert np.array_equal(oracle.interior(g.numpy(), H), oracle.interior(e.numpy(), H)), \
+                    "replay %d output %d" % (r, q)

@@ -9,8 +9,9 @@ test_gpu_parity and test_gpu_half), give the device path's bits, write only
 interior columns of the host outputs, and order itself on the caller's
 stream.  Shapes include odd ny and odd nz with halo 1 and 2, whose 16-bit
 output rows are not a multiple of 4 bytes long, for each way the outputs come
-back: pinned memory through the runtime's copies (the default) or through the
-library's copy kernel, and pageable memory.
+back: pinned memory through the runtime's copies, through the library's copy
+kernel, written by the advection kernel itself, or by whichever of these the
+automatic mode (the default) picks, and pageable memory.
 """
 import numpy as np
 import pytest
@@ -37,7 +38,9 @@ SHAPES = [((20, 13, 64, 2, 31), (1, 3, 7, 20)),
           ((5, 7, 3, 2, 35), (2, 5)),
           ((9, 7, 3, 1, 36), (2, 4)),
           ((6, 5, 3, 1, 34), (5,))]
-MODES = ["pinned_runtime_copy", "pinned_copy_kernel", "pageable"]
+MODES = ["pinned_runtime_copy", "pinned_copy_kernel", "pinned_direct", "pinned_auto", "pageable"]
+COPY_OUT = {"pinned_runtime_copy": "runtime", "pinned_copy_kernel": "kernel", "pinned_direct": "direct",
+            "pinned_auto": "auto", "pageable": "auto"}
 
 
 @pytest.fixture(scope="module")
@@ -89,7 +92,7 @@ def test_offload_matches_oracle(pw, shape, chunks, kind, mode):
         outs = [torch.full(host_in[0].shape, float("nan"), dtype=dtype, pin_memory=pinned) for _ in range(3)]
         ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, h, dtype, chunk, compute=compute),
                          dtype=torch.uint8, device=DEV)
-        with pw.tuning(copy_out="kernel" if mode == "pinned_copy_kernel" else "runtime"):
+        with pw.tuning(copy_out=COPY_OUT[mode]):
             pw.fwd_host(*host_in, t1, t2, tcx, tcy, h, *outs, chunk, ws, compute=compute)
         torch.cuda.current_stream().synchronize()
         for q, got in enumerate(outs):
@@ -100,7 +103,7 @@ def test_offload_matches_oracle(pw, shape, chunks, kind, mode):
             assert np.all(np.isnan(g[:, :h])) and np.all(np.isnan(g[:, -h:]))        # y halo columns
 
 
-@pytest.mark.parametrize("copy_out", ["kernel", "runtime"])
+@pytest.mark.parametrize("copy_out", ["kernel", "runtime", "direct", "auto"])
 def test_offload_orders_on_callers_stream(pw, copy_out):
     """Work queued on the stream before the call (a device copy into the
     pinned inputs) is seen by the offload, and work queued after it (a copy
