@@ -753,9 +753,12 @@ void go_tall(const MarchArgs<T, NF>& m, const Geom& g, int lx, int order, hipStr
 //     (at 4096 x 4096 x 64 19.61 ms mean over six placements, against 20.00
 //     ms in XCD ranges and 19.95 ms for 6-column strips with halo waves; at
 //     256 x 256 x 64 and 512 x 512 x 64 10% faster than the latter, as all 8
-//     waves compute); the FP64 adjoint: 6-column strips with halo waves in
-//     XCD ranges.  Their 150-240 registers allow only 8 or 12 wavefronts per
-//     unit;
+//     waves compute); the FP64 adjoint: 10-column strips with halo waves in
+//     natural order (12 wavefronts, all that its 151 registers allow per
+//     unit: over arrays in one allocation 13.87-14.27 ms against 13.95-14.53
+//     ms for 6-column strips in XCD ranges, in four placements on two
+//     machines; about even over separately allocated arrays).  Their 150-240
+//     registers allow only 8 or 12 wavefronts per unit;
 //   * FP32 fused pass and adjoint, and the accumulating update of both: 14
 //     columns with halo waves in XCD ranges (the FP32 fused pass runs at the
 //     speed of a plain copy of its twelve streams; the FP64 accumulating
@@ -792,7 +795,7 @@ template <typename T, typename C, int NF, bool WS, int UPD>
 int default_variant()
 {
     if (edge16_natural<T, C, NF, WS, UPD>()) return 6;
-    if (NF == 6 && sizeof(T) == 8) return WS ? 5 : 0;
+    if (NF == 6 && sizeof(T) == 8) return WS ? 5 : 4;
     if (NF == 6 && sizeof(C) == 8) return WS ? 5 : 4;
     if (sizeof(T) == 2) {
         if (NF == 6 && !WS) return 5;
@@ -807,7 +810,7 @@ int default_variant()
 template <typename T, typename C, int NF, bool WS, int UPD>
 int default_order()
 {
-    return (edge16_natural<T, C, NF, WS, UPD>() || (NF == 6 && WS && sizeof(T) == 8)) ? 1 : 0;
+    return (edge16_natural<T, C, NF, WS, UPD>() || (NF == 6 && sizeof(T) == 8)) ? 1 : 0;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
