@@ -152,6 +152,17 @@ def time_launches(torch, fn, reps):
     return [ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]
 
 
+def settle(torch, fn, seconds=None):
+    """Untimed launches of fn for `seconds` (default CLOCK_SETTLE_S): after
+    an idle period (allocating and filling a new grid) the GPU runs these
+    kernels near 1.5 GHz and ramps its clock up over their first launches
+    (about 0.1 s), which would otherwise fall into a short timed run."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < (CLOCK_SETTLE_S if seconds is None else seconds):
+        fn()
+        torch.cuda.synchronize()
+
+
 def path_record(path, esize, cells, times_ms):
     ts = sorted(times_ms)
     avg = sum(times_ms) / len(times_ms)
@@ -474,10 +485,7 @@ def main():
     # its clock up over their first 5-8 launches (about 0.1 s); let it settle
     # before the warm-up launches, so that the timed launches all see the
     # clock the workload holds.
-    t_settle = time.perf_counter()
-    while time.perf_counter() - t_settle < CLOCK_SETTLE_S:
-        g.launch(pw, "fused")
-        torch.cuda.synchronize()
+    settle(torch, lambda: g.launch(pw, "fused"))
     for _ in range(args.warmup):
         g.launch(pw, "fused")
     torch.cuda.synchronize()
@@ -510,6 +518,7 @@ def main():
     if not args.no_paths and not args.no_separate:
         g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True, pooled=False)
         separate = {"layout": "one allocation per array"}
+        settle(torch, lambda: g.launch(pw, "fused"))
         for p in ("fused", "fwd"):
             g.launch(pw, p)
             separate[p + "_f64"] = path_record(p, 8, cells, time_launches(torch, lambda: g.launch(pw, p),
@@ -521,6 +530,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_paths:
         g = Grid(pw, torch, nx, ny, nz, h, torch.float32, seed, True)
+        settle(torch, lambda: g.launch(pw, "fused"))
         for p in ("fwd", "adj", "fused"):
             g.launch(pw, p)
             paths[p + "_f32"] = path_record(p, 4, cells, time_launches(torch, lambda: g.launch(pw, p),
@@ -530,6 +540,7 @@ def main():
         torch.cuda.empty_cache()
         # FP32 storage with FP64 arithmetic
         g = Grid(pw, torch, nx, ny, nz, h, torch.float32, seed, True, compute=torch.float64)
+        settle(torch, lambda: g.launch(pw, "fused"))
         for p in ("fwd", "adj", "fused"):
             g.launch(pw, p)
             paths[p + "_f32f64"] = path_record(p, 4, cells, time_launches(torch, lambda: g.launch(pw, p),
@@ -540,6 +551,7 @@ def main():
         # 16-bit storage, float arithmetic
         for tag, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
             g = Grid(pw, torch, nx, ny, nz, h, dt, seed, True)
+            settle(torch, lambda: g.launch(pw, "fused"))
             for p in ("fwd", "adj", "fused"):
                 g.launch(pw, p)
                 paths[p + "_" + tag] = path_record(p, 2, cells, time_launches(torch, lambda: g.launch(pw, p),
@@ -560,6 +572,7 @@ def main():
         cm = wm["nx"] * wm["ny"] * wm["nz"]
         medium = {"workload": "medium %dx%dx%d FP64, 100 launches each" % (wm["nx"], wm["ny"], wm["nz"]),
                   "note": "fwd working set 221 MB fits the 256 MB Infinity Cache: not an HBM rate"}
+        settle(torch, lambda: [g.launch(pw, "fused") for _ in range(20)])
         for p in ("fwd", "fused"):
             g.launch(pw, p)
             medium[p] = path_record(p, 8, cm, time_launches(torch, lambda: g.launch(pw, p), 100))
@@ -574,6 +587,7 @@ def main():
         precision = {"workload": "precision %dx%dx%d, 20 launches each" % (wp["nx"], wp["ny"], wp["nz"])}
         for tag, dt, esz in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
             g = Grid(pw, torch, wp["nx"], wp["ny"], wp["nz"], h, dt, wp["seed"], True)
+            settle(torch, lambda: [g.launch(pw, "fused") for _ in range(4)])
             for p in ("fwd", "adj", "fused"):
                 g.launch(pw, p)
                 precision[p + "_" + tag] = path_record(p, esz, cp, time_launches(torch, lambda: g.launch(pw, p), 20))
