@@ -598,6 +598,25 @@ def main():
         log("bench: 1024^2 fwd f64 %.0f GB/s, f32 %.0f GB/s" % (precision["fwd_f64"]["alg_GBps"],
                                                              precision["fwd_f32"]["alg_GBps"]))
 
+    # columns of 128 levels (two wavefronts per column in the marching
+    # kernels), FP64 and FP32, 2048 x 2048 x 128: the same cells per plane
+    # as the headline grid's quarter, twice the levels
+    tall = None
+    if not args.no_paths:
+        tnx, tny, tnz, tseed = 2048, 2048, 128, 5
+        ct = tnx * tny * tnz
+        tall = {"workload": "tall columns %dx%dx%d, 10 launches each" % (tnx, tny, tnz)}
+        for tag, dt, esz in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            g = Grid(pw, torch, tnx, tny, tnz, h, dt, tseed, True)
+            settle(torch, lambda: g.launch(pw, "fused"))
+            for p in ("fwd", "adj", "fused"):
+                g.launch(pw, p)
+                tall[p + "_" + tag] = path_record(p, esz, ct, time_launches(torch, lambda: g.launch(pw, p), 10))
+            del g
+            torch.cuda.empty_cache()
+        log("bench: 2048^2 x 128 fwd f64 %.2f ms (%.0f GB/s), fused f64 %.2f ms" % (
+            tall["fwd_f64"]["ms_avg"], tall["fwd_f64"]["alg_GBps"], tall["fused_f64"]["ms_avg"]))
+
     kname = "fused_f64"
     traffic = measured_traffic(kname, args.workload)
     achieved = head["alg_GBps"]
@@ -622,6 +641,7 @@ def main():
         "copy_reference": copy_ref,
         "separate_allocations": separate,
         "precision_workload": precision,
+        "tall_columns": tall,
         "medium_cache_resident": medium,
         "source_hash": kernel_source_hash(),
         "clock_settle_s": CLOCK_SETTLE_S,
