@@ -749,16 +749,17 @@ void go_tall(const MarchArgs<T, NF>& m, const Geom& g, int lx, int order, hipStr
 //     9.22-10.28, against 10.02 ms for 14-column strips with halo waves in
 //     XCD ranges and 10.59 ms, range 9.14-11.48, for those in natural order;
 //     FP32 5.01 against 5.13 ms);
-//   * the FP64 fused pass: 8-column strips with edge waves in natural order
-//     (at 4096 x 4096 x 64 19.61 ms mean over six placements, against 20.00
+//   * the FP64 fused pass: 8-column strips with edge waves, pairs of strips
+//     per XCD (natural order: 19.61 ms mean over six placements, against 20.00
 //     ms in XCD ranges and 19.95 ms for 6-column strips with halo waves; at
 //     256 x 256 x 64 and 512 x 512 x 64 10% faster than the latter, as all 8
 //     waves compute); the FP64 adjoint: 10-column strips with halo waves in
-//     natural order (12 wavefronts, all that its 151 registers allow per
-//     unit: over arrays in one allocation 13.87-14.27 ms against 13.95-14.53
-//     ms for 6-column strips in XCD ranges, in four placements on two
-//     machines; about even over separately allocated arrays).  Their 150-240
-//     registers allow only 8 or 12 wavefronts per unit;
+//     groups of 8 strips per XCD (12 wavefronts, all that its 151 registers
+//     allow per unit; in natural order, over arrays in one allocation,
+//     13.87-14.27 ms against 13.95-14.53 ms for 6-column strips in XCD
+//     ranges, in four placements on two machines; about even over separately
+//     allocated arrays).  Their 150-240 registers allow only 8 or 12
+//     wavefronts per unit;
 //   * FP32 fused pass and adjoint, and the accumulating update of both: 14
 //     columns with halo waves in XCD ranges (the FP32 fused pass runs at the
 //     speed of a plain copy of its twelve streams; the FP64 accumulating
@@ -806,11 +807,17 @@ int default_variant()
 }
 
 // Default block order of the default variant: 0 for XCD ranges, G > 0 for
-// groups of G strips per XCD (1: natural order).
+// groups of G strips per XCD (1: natural order).  The FP64 fused pass takes
+// pairs of strips per XCD and the FP64 adjoint groups of 8: most halo columns
+// then stay in one XCD's L2 while the device still sweeps one window of the
+// grid (at 4096 x 4096 x 64 over arrays in one allocation, two placements:
+// fused 19.16 and 19.34 ms against 19.30 and 20.16 ms in natural order,
+// adjoint 14.25 and 14.13 ms against 14.41 and 14.57 ms).
 template <typename T, typename C, int NF, bool WS, int UPD>
 int default_order()
 {
-    return (edge16_natural<T, C, NF, WS, UPD>() || (NF == 6 && sizeof(T) == 8)) ? 1 : 0;
+    if (NF == 6 && sizeof(T) == 8) return WS ? 2 : 8;
+    return edge16_natural<T, C, NF, WS, UPD>() ? 1 : 0;
 }
 
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
