@@ -817,6 +817,9 @@ template <typename T, typename C, int NF, bool WS, int UPD>
 int default_order()
 {
     if (NF == 6 && sizeof(T) == 8) return WS ? 2 : 8;
+    // the 16-bit forward and Euler update in groups of 16 strips: 1-1.6%
+    // faster than XCD ranges in each of five placements
+    if (sizeof(T) == 2 && NF == 3 && UPD != 1) return 16;
     return edge16_natural<T, C, NF, WS, UPD>() ? 1 : 0;
 }
 
