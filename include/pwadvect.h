@@ -121,21 +121,29 @@ enum {
                                   type and output set [-1].  Variants 0..6 hold
                                   one wavefront per column and cut columns of
                                   more than 64 levels into z-chunks; variant
-                                  PW_MARCH_VARIANTS-1 holds a column of 65..256
-                                  levels in 2 to 4 wavefronts of one workgroup
-                                  (the default for such columns; for other
-                                  columns it selects the default variant) */
+                                  PW_MARCH_VARIANTS-1 holds a column of more
+                                  than 64 levels in 2 to 4 wavefronts of one
+                                  workgroup, a column of more than 256 levels
+                                  in z-chunks of 64 * waves - 2 levels (the
+                                  default for such columns; for other columns
+                                  it selects the default variant) */
     PW_TUNE_MARCH_LX = 2,      /* x-planes per marching workgroup, or 0 to choose
                                   from the grid [0] */
     PW_TUNE_COPY_OUT = 3,      /* how pw_advect_fwd_host returns the source terms,
                                   PW_COPY_OUT_* [PW_COPY_OUT_AUTO] */
-    PW_TUNE_BLOCK_ORDER = 4    /* order of the x-marching workgroups over the
+    PW_TUNE_BLOCK_ORDER = 4,   /* order of the x-marching workgroups over the
                                   strips: PW_ORDER_XCD, or G in
                                   1..PW_ORDER_MAX_GROUP for groups of G
                                   neighbouring strips per XCD, the 8 XCDs
                                   interleaved group by group (1: natural
                                   order), or -1 for the measured default of
                                   each kernel [-1] */
+    PW_TUNE_TALL_WAVES = 5     /* wavefronts per column of variant
+                                  PW_MARCH_VARIANTS-1, 2..4, or 0 for the
+                                  fewest that hold a column of up to 256
+                                  levels and, above that, the most whose
+                                  z-chunks idle at most 10% more lanes than
+                                  the chunking that idles fewest [0] */
 };
 enum {
     PW_ORDER_XCD = 0,       /* each of the 8 XCDs takes one contiguous range of strips */

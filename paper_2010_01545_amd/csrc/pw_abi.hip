@@ -23,10 +23,11 @@ struct Tuning {
     int lx = 0;                       // 0: segment length from the grid
     int copy_out = PW_COPY_OUT_AUTO;
     int order = -1;                   // < 0: default block order, 0: XCD ranges, G: groups of G
+    int tall_waves = 0;               // 0: wavefronts per tall column chosen from nz
 };
 thread_local Tuning g_tune;
 
-MarchTune march_tune() { return MarchTune{g_tune.variant, g_tune.lx, g_tune.order}; }
+MarchTune march_tune() { return MarchTune{g_tune.variant, g_tune.lx, g_tune.order, g_tune.tall_waves}; }
 
 int fail(int code, const char* fmt, ...)
 {
@@ -614,6 +615,11 @@ int pw_set_tuning(int knob, int value)
             return fail(PW_ERR_ARG, "block order %d outside -1..%d", value, PW_ORDER_MAX_GROUP);
         g_tune.order = value;
         break;
+    case PW_TUNE_TALL_WAVES:
+        if (value != 0 && (value < 2 || value > 4))
+            return fail(PW_ERR_ARG, "wavefronts per tall column %d: need 0 (automatic) or 2..4", value);
+        g_tune.tall_waves = value;
+        break;
     default:
         return fail(PW_ERR_ARG, "unknown tuning knob %d", knob);
     }
@@ -629,6 +635,7 @@ int pw_get_tuning(int knob, int* value)
     case PW_TUNE_MARCH_LX: *value = g_tune.lx; break;
     case PW_TUNE_COPY_OUT: *value = g_tune.copy_out; break;
     case PW_TUNE_BLOCK_ORDER: *value = g_tune.order; break;
+    case PW_TUNE_TALL_WAVES: *value = g_tune.tall_waves; break;
     default: return fail(PW_ERR_ARG, "unknown tuning knob %d", knob);
     }
     return ok();

@@ -46,11 +46,13 @@ template <typename T, typename C> void launch_adj_direct(const AdjArgs<T>& a, co
 // columns shorter than 1 GiB).  MarchTune carries the calling thread's
 // choice of variant (< 0: the default for the type pair and output set),
 // segment length in planes (0: chosen from the grid) and block order (< 0:
-// the default; 0: XCD ranges; 1: natural).
+// the default; 0: XCD ranges; 1: natural) and wavefronts per column of the
+// tall variant (0: chosen from nz).
 struct MarchTune {
     int variant;
     int lx;
     int order;
+    int tall_waves;
 };
 template <typename T> bool march_supported(const Geom& g);
 template <typename T, typename C>

@@ -17,16 +17,18 @@
 //     ring.  With TY a multiple of 4 the arithmetic spreads evenly over the
 //     four SIMDs of a compute unit, which pays where the arithmetic, not HBM,
 //     sets the pace.
-// Columns of 65 to 256 levels are held by ZW = 2, 3 or 4 wavefronts of one
-// workgroup, wave z holding levels 64 z .. 64 z + 63.  Their z-neighbours
-// come from the LDS ring instead of wavefront shifts: it then holds whole
-// columns, with a zero entry below level 0 and above the top, and keeps
-// three planes of every field, so that plane p+1 of a neighbouring wave's
-// levels is there when step p needs it.  Taller columns still are cut into
-// z-chunks of 62 levels, one chunk per workgroup: lane l holds level
-// 62 c - 1 + l, lanes 0 and 63 are the chunk's halo levels (loaded, never
-// stored), so the z-neighbours of lanes 1..62 still come from wavefront
-// shifts.
+// Columns of more than 64 levels are held by ZW = 2, 3 or 4 wavefronts of
+// one workgroup (variant 7, the default for them), wave z holding levels
+// 64 z .. 64 z + 63.  Their z-neighbours come from the LDS ring instead of
+// wavefront shifts: it then holds whole columns, with a zero entry below
+// level 0 and above the top, and keeps three planes of every field, so that
+// plane p+1 of a neighbouring wave's levels is there when step p needs it.
+// Columns of more than 256 levels are cut into z-chunks of 64 ZW - 2 levels,
+// one per workgroup, whose first and last lanes hold the neighbouring
+// chunks' levels (loaded, never stored).  Variants 0-6 cut every column of
+// more than 64 levels into z-chunks of 62 levels, one wavefront each: lane l
+// holds level 62 c - 1 + l, lanes 0 and 63 are the chunk's halo levels, so
+// the z-neighbours of lanes 1..62 still come from wavefront shifts.
 //
 // Reuse.  Each field (u, v, w and, for the adjoint, lu, lv, lw) is read from
 // HBM once per cell:
@@ -239,7 +241,8 @@ struct MarchArgs {
 // itself: each element is read planes before the same wave writes it); 2 the
 // same with b = (u, v, w), whose centre values are already in the ring.
 // ZW: wavefronts per column (1, or 2, 3 or 4 for columns of up to 128, 192
-// or 256 levels, whose z-neighbours then come from the LDS ring).
+// or 256 levels or for chunks of 64 ZW - 2 levels of taller ones, whose
+// z-neighbours then come from the LDS ring).
 template <typename T, typename C, int NF, bool WS, bool WG, int TY, int D, bool EH, int UPD = 0, int ZW = 1>
 __global__ void __launch_bounds__(64 * (EH ? TY : TY + 2) * ZW)
 march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nblocks, int group)
@@ -312,16 +315,24 @@ march_kernel(MarchArgs<T, NF> a, Geom g, int LX, int nstrips, int nchunk, int nb
         return f + ((long long)(pc + g.h) * sx + (long long)(j + dj + g.h) * sy);
     };
     // level of this lane; loads at levels outside 0..nz-1 are out of range
-    // (read zero), stores only from the lanes the chunk owns
-    const int k = ZL ? NZ * zw + lane : nchunk == 1 ? lane : chunk * kChunk - 1 + lane;
-    const bool own = ZL || nchunk == 1 || (lane >= 1 && lane <= kChunk);
-    const int lk = ZL ? 1 + k : lane;   // this lane's LDS entry
+    // (read zero), stores only from the lanes the chunk owns.  With ZW > 1 a
+    // column taller than NZ * ZW levels is cut into z-chunks of NZ * ZW - 2
+    // levels, one per workgroup: the first lane of wave 0 and the last lane
+    // of wave ZW - 1 hold the chunk's halo levels (loaded, never stored), so
+    // every owned level finds its z-neighbours in the LDS column.
+    constexpr int kChunkZ = NZ * ZW - 2;
+    const int kl = NZ * zw + lane;      // level within the chunk's window (ZW > 1)
+    const int k = ZL ? (nchunk == 1 ? kl : chunk * kChunkZ - 1 + kl)
+                     : nchunk == 1 ? lane : chunk * kChunk - 1 + lane;
+    const bool own = ZL ? (nchunk == 1 || (kl >= 1 && kl <= kChunkZ))
+                        : (nchunk == 1 || (lane >= 1 && lane <= kChunk));
+    const int lk = ZL ? 1 + kl : lane;  // this lane's LDS entry
     const unsigned voff = (k >= 0 && k < g.nz) ? (unsigned)(g.h + k) * (unsigned)sizeof(T) : kOutOfRange;
     const unsigned vst = own ? voff : kOutOfRange;
     // z-halo levels of an output column: lanes 0..h-1 bottom (first chunk),
     // h..2h-1 top (last chunk)
-    const bool first_z = ZL ? zw == 0 : chunk == 0;
-    const bool last_z = ZL ? zw == ZW - 1 : chunk == nchunk - 1;
+    const bool first_z = chunk == 0 && (!ZL || zw == 0);
+    const bool last_z = chunk == nchunk - 1 && (!ZL || zw == ZW - 1);
     const unsigned vpad = (lane < g.h && first_z) ? (unsigned)lane * (unsigned)sizeof(T)
                         : (lane >= g.h && lane < 2 * g.h && last_z)
                               ? (unsigned)(g.nz + lane) * (unsigned)sizeof(T) : kOutOfRange;
@@ -607,7 +618,8 @@ Launch plan(const Geom& g, int TY, int lx, int slots, int order, int zw = 1)
 {
     Launch l;
     l.nstrips = (g.ny + TY - 1) / TY;
-    l.nchunk = g.nz <= NZ * zw ? 1 : (g.nz + kChunk - 1) / kChunk;
+    const int chunk_levels = zw > 1 ? NZ * zw - 2 : kChunk;
+    l.nchunk = g.nz <= NZ * zw ? 1 : (g.nz + chunk_levels - 1) / chunk_levels;
     const long long cols = (long long)l.nstrips * l.nchunk;
     if (lx <= 0) {
         long long best = -1;
@@ -669,7 +681,7 @@ constexpr int lds_bytes()
                    : (int)sizeof(work_t<T, C>) * (2 * (NF / 3) * 3 + (NF / 3) * 3) * (TY + 2) * (NZ * ZW + 2);
 }
 
-// Columns of 65 to 256 levels (PW_MARCH_VARIANTS - 1, the default there):
+// Columns of more than 64 levels (PW_MARCH_VARIANTS - 1, the default there):
 // ZW = 2, 3 or 4 wavefronts per column, edge waves, D = 2, 16 (15 with
 // ZW = 3) wavefronts per workgroup for the forward and 8 (6) for the
 // six-field kernels (whose registers allow 8 per compute unit).  At 2048 x 2048 x 128 FP64 the
@@ -826,14 +838,32 @@ int default_order()
 template <typename T, typename C, int NF, bool WS, bool WG, int UPD = 0>
 void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t s)
 {
-    if (g.nz > NZ && g.nz <= 4 * NZ && (t.variant < 0 || t.variant == kTallVariant)) {
-        // natural order for the two-wavefront forward (3-7% faster at 100 and
-        // 128 levels), XCD ranges for the rest (natural is up to 8% slower for
-        // the six-field kernels at 200 and 256 levels)
-        const int order = t.order >= 0 ? t.order : (NF == 3 && g.nz <= 2 * NZ) ? 1 : 0;
-        if (g.nz <= 2 * NZ)
+    if (g.nz > NZ && (t.variant < 0 || t.variant == kTallVariant)) {
+        // wavefronts per column: the fewest that hold it (up to 256 levels),
+        // else the most whose chunks of NZ * ZW - 2 levels idle at most 10%
+        // more lanes than the chunking that idles fewest (longer chunks read
+        // longer runs of each column: at 400 levels two chunks of four
+        // wavefronts, not four of two)
+        int zw = g.nz <= 2 * NZ ? 2 : g.nz <= 3 * NZ ? 3 : 4;
+        if (t.tall_waves >= 2 && t.tall_waves <= 4) {
+            zw = t.tall_waves;
+        } else if (g.nz > 4 * NZ) {
+            long long lanes[5] = {0, 0, 0, 0, 0}, fewest = -1;
+            for (int z = 2; z <= 4; ++z) {
+                const long long per = NZ * z - 2;
+                lanes[z] = (g.nz + per - 1) / per * per;
+                if (fewest < 0 || lanes[z] < fewest) fewest = lanes[z];
+            }
+            for (int z = 2; z <= 4; ++z)
+                if (lanes[z] * 10 <= fewest * 11) zw = z;
+        }
+        // natural order for the two-wavefront forward (3-11% faster at 100,
+        // 128, 300 and 400 levels), XCD ranges for the rest (natural is up to
+        // 8% slower for the six-field kernels at 200 and 256 levels)
+        const int order = t.order >= 0 ? t.order : (NF == 3 && zw == 2) ? 1 : 0;
+        if (zw == 2)
             go_tall<T, C, NF, WS, WG, UPD, 2>(m, g, t.lx, order, s);
-        else if (g.nz <= 3 * NZ)
+        else if (zw == 3)
             go_tall<T, C, NF, WS, WG, UPD, 3>(m, g, t.lx, order, s);
         else
             go_tall<T, C, NF, WS, WG, UPD, 4>(m, g, t.lx, order, s);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libpwadvect.so")
 PW_F64, PW_F32, PW_F32_F64, PW_F16, PW_BF16 = 0, 1, 2, 3, 4
 KERNELS = {"auto": 0, "direct": 1, "march": 2}
 # tuning knobs of the calling thread (pw_set_tuning)
-TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT, TUNE_BLOCK_ORDER = 0, 1, 2, 3, 4
+TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT, TUNE_BLOCK_ORDER, TUNE_TALL_WAVES = 0, 1, 2, 3, 4, 5
 MARCH_VARIANTS = 8
 COPY_OUT = {"runtime": 0, "kernel": 1, "direct": 2, "auto": 3}
 ORDERS = {"default": -1, "xcd": 0, "natural": 1}   # or an int G: groups of G strips per XCD
@@ -330,9 +330,10 @@ class tuning:
     Keywords: kernel ('auto', 'direct', 'march'), variant (-1..7), lx (planes
     per marching workgroup, 0 = automatic), copy_out ('runtime', 'kernel', 'direct', 'auto'),
     order ('default', 'xcd', 'natural', or an int G: groups of G neighbouring
-    strips per XCD)."""
+    strips per XCD), tall_waves (wavefronts per column of the tall variant,
+    2..4, 0 = automatic)."""
 
-    def __init__(self, kernel=None, variant=None, lx=None, copy_out=None, order=None):
+    def __init__(self, kernel=None, variant=None, lx=None, copy_out=None, order=None, tall_waves=None):
         self.want = []
         if kernel is not None:
             self.want.append((TUNE_KERNEL, KERNELS[kernel]))
@@ -344,6 +345,8 @@ class tuning:
             self.want.append((TUNE_COPY_OUT, COPY_OUT[copy_out]))
         if order is not None:
             self.want.append((TUNE_BLOCK_ORDER, ORDERS[order] if isinstance(order, str) else int(order)))
+        if tall_waves is not None:
+            self.want.append((TUNE_TALL_WAVES, int(tall_waves)))
         self.saved = []
 
     def __enter__(self):

@@ -185,7 +185,8 @@ def test_utility_checks(lib):
 
 
 # ---------------------------------------------------------------- tuning knobs
-PW_TUNE_KERNEL, PW_TUNE_MARCH_VARIANT, PW_TUNE_MARCH_LX, PW_TUNE_COPY_OUT, PW_TUNE_BLOCK_ORDER = 0, 1, 2, 3, 4
+PW_TUNE_KERNEL, PW_TUNE_MARCH_VARIANT, PW_TUNE_MARCH_LX, PW_TUNE_COPY_OUT, PW_TUNE_BLOCK_ORDER, PW_TUNE_TALL_WAVES = \
+    0, 1, 2, 3, 4, 5
 
 
 def _get(lib, knob):
@@ -197,11 +198,12 @@ def _get(lib, knob):
 def test_tuning_knobs_set_get_and_reject(lib):
     lib.pw_get_tuning.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     defaults = {PW_TUNE_KERNEL: 0, PW_TUNE_MARCH_VARIANT: -1, PW_TUNE_MARCH_LX: 0, PW_TUNE_COPY_OUT: 3,
-                PW_TUNE_BLOCK_ORDER: -1}
+                PW_TUNE_BLOCK_ORDER: -1, PW_TUNE_TALL_WAVES: 0}
     for knob, d in defaults.items():
         assert _get(lib, knob) == (PW_OK, d)
     for knob, good, bad in ((PW_TUNE_KERNEL, 2, 3), (PW_TUNE_MARCH_VARIANT, 7, 8),
-                            (PW_TUNE_MARCH_LX, 9, -1), (PW_TUNE_COPY_OUT, 2, 4), (PW_TUNE_BLOCK_ORDER, 16, 65537)):
+                            (PW_TUNE_MARCH_LX, 9, -1), (PW_TUNE_COPY_OUT, 2, 4), (PW_TUNE_BLOCK_ORDER, 16, 65537),
+                            (PW_TUNE_TALL_WAVES, 3, 5)):
         assert lib.pw_set_tuning(knob, good) == PW_OK
         assert _get(lib, knob) == (PW_OK, good)
         assert lib.pw_set_tuning(knob, bad) == PW_ERR_ARG
@@ -209,6 +211,7 @@ def test_tuning_knobs_set_get_and_reject(lib):
         assert lib.pw_set_tuning(knob, defaults[knob]) == PW_OK
     assert lib.pw_set_tuning(PW_TUNE_MARCH_VARIANT, -2) == PW_ERR_ARG
     assert lib.pw_set_tuning(PW_TUNE_BLOCK_ORDER, -2) == PW_ERR_ARG
+    assert lib.pw_set_tuning(PW_TUNE_TALL_WAVES, 1) == PW_ERR_ARG
     assert lib.pw_set_tuning(17, 0) == PW_ERR_ARG
     assert _get(lib, 17)[0] == PW_ERR_ARG
     assert lib.pw_get_tuning(PW_TUNE_KERNEL, None) == PW_ERR_ARG

@@ -1,11 +1,11 @@
-"""GPU tests of the x-marching kernels for columns of 65 to 256 levels, held
-by two or four wavefronts of one workgroup whose z-neighbours come from the
-LDS ring: bit for bit against the direct kernel (which is tested against the
-oracle in test_gpu_parity), forward, adjoint, fused pass and both update
-forms, for every storage type, at heights on both sides of 128 and 192 and
-at 256,
-with several x-segments, narrow last strips, three block orders and halo
-widths 1 to 3; and once against the oracle itself."""
+"""GPU tests of the x-marching kernels for columns of more than 64 levels,
+held by two to four wavefronts of one workgroup (in z-chunks above 256
+levels) whose z-neighbours come from the LDS ring: bit for bit against the
+direct kernel (which is tested against the oracle in test_gpu_parity),
+forward, adjoint, fused pass and both update forms, for every storage type,
+at heights on both sides of 128, 192 and 256 and in chunks of each
+wavefront count, with several x-segments, narrow last strips, three block
+orders and halo widths 1 to 3; and once against the oracle itself."""
 import numpy as np
 import pytest
 import torch
@@ -62,12 +62,15 @@ def _same(a, b):
     return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(np.nan_to_num(a), np.nan_to_num(b))
 
 
-@pytest.mark.parametrize("nz", [65, 100, 128, 129, 150, 192, 193, 256])
+@pytest.mark.parametrize("nz", [65, 100, 128, 129, 150, 192, 193, 256, 257, 400, 508, 509])
 @pytest.mark.parametrize("kind", list(KINDS))
 def test_tall_columns_match_direct(pw, kind, nz):
     """Default kernel selection (two wavefronts per column up to 128 levels,
-    three up to 192, four up to 256) against the direct kernel, with x-segments of 5 planes
-    and ny = 11, which leaves a last strip narrower than the strip width."""
+    three up to 192, four up to 256; above that z-chunks of 126, 190 or 254
+    levels: 257 levels in two chunks of three wavefronts, 400 and 508 in two
+    of four, 509 in three of three) against the direct kernel, with
+    x-segments of 5 planes and ny = 11, which leaves a last strip narrower
+    than the strip width."""
     dtype, compute = KINDS[kind]
     nx, ny, h, seed = 13, 11, 2, 300 + nz
     log("tall %s nz=%d" % (kind, nz))
@@ -80,7 +83,8 @@ def test_tall_columns_match_direct(pw, kind, nz):
 
 
 @pytest.mark.parametrize("order", ["xcd", "natural", 2])
-@pytest.mark.parametrize("shape", [(9, 7, 100, 1), (6, 5, 256, 1), (7, 9, 150, 3), (5, 3, 70, 3), (6, 11, 180, 2)],
+@pytest.mark.parametrize("shape", [(9, 7, 100, 1), (6, 5, 256, 1), (7, 9, 150, 3), (5, 3, 70, 3), (6, 11, 180, 2),
+                                   (5, 6, 300, 3)],
                          ids=lambda s: "x".join(map(str, s[:3])) + "h%d" % s[3])
 def test_tall_orders_and_halos(pw, shape, order):
     """Block orders and halo widths 1 and 3 (the edge waves address their
@@ -95,6 +99,25 @@ def test_tall_orders_and_halos(pw, shape, order):
                        dict(lx=lx, order=order, variant=pw.MARCH_VARIANTS - 1))
             for q, (a, b) in enumerate(zip(ref, got)):
                 assert _same(a, b), (path, lx, q)
+
+
+@pytest.mark.parametrize("waves", [2, 3, 4])
+@pytest.mark.parametrize("nz", [65, 130, 255, 300, 520])
+@pytest.mark.parametrize("kind", ["f64", "f32", "bf16"])
+def test_tall_wave_counts(pw, kind, nz, waves):
+    """Each count of wavefronts per column, chosen with the tuning knob, at
+    heights that one workgroup holds with idle lanes and at heights cut into
+    two to five z-chunks (520 levels: five chunks of 126, three of 190, three
+    of 254), forward, adjoint and fused pass against the direct kernel."""
+    dtype, compute = KINDS[kind]
+    nx, ny, h, seed = 7, 9, 2, 500 + nz + waves
+    log("tall waves %d %s nz=%d" % (waves, kind, nz))
+    fields, lams, coef = host_case(nx, ny, nz, seed, lam_seed=seed + 1)
+    for path in ("fwd", "adj", "fused"):
+        ref = _run(pw, fields, lams, coef, dtype, compute, h, path, "direct", {})
+        got = _run(pw, fields, lams, coef, dtype, compute, h, path, "march", dict(lx=4, tall_waves=waves))
+        for q, (a, b) in enumerate(zip(ref, got)):
+            assert _same(a, b), (path, q)
 
 
 def test_tall_columns_match_oracle(pw):
