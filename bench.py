@@ -181,16 +181,17 @@ def path_record(path, esize, cells, times_ms):
 # untimed launches of the headline kernel before its warm-up (seconds)
 CLOCK_SETTLE_S = 0.3
 
-# launch shapes of the streaming copy: (bytes per thread and array, workgroups; 0 = one pass)
-COPY_SHAPES = ((4, 0), (8, 0), (16, 0), (16, 2048))
+# launch shapes of the streaming copy: (bytes per thread and array, workgroups (0 = one pass),
+# cache hints: 1 non-temporal loads, 2 non-temporal stores)
+COPY_SHAPES = ((4, 0, 0), (4, 0, 1), (4, 0, 2), (4, 0, 3), (8, 0, 0), (16, 0, 0), (16, 0, 3), (16, 2048, 0))
 
 
 def copy_reference(pw, torch, g, reps=5):
     """The library's plain streaming copy (pw_stream_copy) over the very
     arrays the headline kernel uses (same placement in HBM): 6 arrays read and
     6 written (the fused pass's streams: u, v, w, lu, lv, lw -> su .. gw) and
-    3 + 3 (the forward's).  Each launch shape is timed; the fastest is the
-    achievable-bandwidth reference.  Timed interleaved with the FP64 fused and
+    3 + 3 (the forward's).  Each launch shape and cache policy is timed; the
+    fastest is the achievable-bandwidth reference.  Timed interleaved with the FP64 fused and
     forward kernels on the same arrays, so that their ratio compares like with
     like."""
     nbytes = g.f[0].numel() * g.f[0].element_size()
@@ -198,21 +199,21 @@ def copy_reference(pw, torch, g, reps=5):
                      "storage arrays of %d bytes" % nbytes}
     for tag, src, dst, path in (("6R6W", g.f + g.l, g.s + g.g, "fused"), ("3R3W", g.f, g.s, "fwd")):
         shapes = {}
-        for unit, b in COPY_SHAPES:
-            pw.stream_copy(src, dst, b, unit)
-            ms = time_launches(torch, lambda: pw.stream_copy(src, dst, b, unit), reps)
-            shapes["unit_%d_blocks_%d" % (unit, b)] = {
+        for unit, b, hints in COPY_SHAPES:
+            pw.stream_copy(src, dst, b, unit, hints)
+            ms = time_launches(torch, lambda: pw.stream_copy(src, dst, b, unit, hints), reps)
+            shapes["unit_%d_blocks_%d_hints_%d" % (unit, b, hints)] = {
                 "ms": sum(ms) / len(ms), "GBps": 2 * len(src) * nbytes / (sum(ms) / len(ms) * 1e-3) / 1e9}
         best = min(shapes, key=lambda k: shapes[k]["ms"])
-        unit, b = (int(x) for x in best.split("_")[1::2])
+        unit, b, hints = (int(x) for x in best.split("_")[1::2])
         # interleaved: copy, kernel, copy, kernel ...
         tc, tk = [], []
         for _ in range(reps):
-            tc += time_launches(torch, lambda: pw.stream_copy(src, dst, b, unit), 1)
+            tc += time_launches(torch, lambda: pw.stream_copy(src, dst, b, unit, hints), 1)
             tk += time_launches(torch, lambda: g.launch(pw, path), 1)
         mc, mk = sum(tc) / len(tc), sum(tk) / len(tk)
         rec[tag] = {"ms": mc, "GBps": 2 * len(src) * nbytes / (mc * 1e-3) / 1e9, "unit": unit, "blocks": b,
-                    "launch_shapes": shapes,
+                    "hints": hints, "launch_shapes": shapes,
                     "interleaved_%s_f64_ms" % path: mk,
                     "%s_f64_time_fraction_of_copy" % path: mc / mk}
         # torch's device copy of the same arrays, for comparison
@@ -424,6 +425,8 @@ def main():
                     "or the streaming copy of 3 or 6 storage arrays (copy3, copy6)")
     ap.add_argument("--copy-blocks", type=int, default=0, help="launch shape of --only copy3/copy6")
     ap.add_argument("--copy-unit", type=int, default=4, help="bytes per thread and array of --only copy3/copy6")
+    ap.add_argument("--copy-hints", type=int, default=0,
+                    help="cache hints of --only copy3/copy6: 1 non-temporal loads, 2 stores, 3 both")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -461,7 +464,7 @@ def main():
         src, dst = (g.f + g.l)[:n], (g.s + g.g)[:n]
         torch.cuda.synchronize()
         for _ in range(args.warmup + args.steps):
-            pw.stream_copy(src, dst, args.copy_blocks, args.copy_unit)
+            pw.stream_copy(src, dst, args.copy_blocks, args.copy_unit, args.copy_hints)
         torch.cuda.synchronize()
         log("bench: profile run of %s done" % args.only)
         return

@@ -91,7 +91,7 @@ def _march_args(mangled):
     if not m:
         return None
     a = m.group(1)
-    types = {"d": "double", "f": "float", "DF16_": "_Float16", "N12_GLOBAL__N_16bf16_tE": "bf16"}
+    types = {"d": "double", "f": "float", "DF16_": "_Float16", "6bf16_t": "bf16", "N12_GLOBAL__N_16bf16_tE": "bf16"}
     out = []
     while a:
         for k in sorted(types, key=len, reverse=True):

@@ -556,13 +556,15 @@ int pw_fill_uniform(void* storage, int nx, int ny, int nz, int halo, unsigned lo
 }
 
 int pw_stream_copy(const void* const* src, void* const* dst, int narrays, size_t bytes, int unit, int blocks,
-                   void* stream)
+                   int hints, void* stream)
 {
     if (!src || !dst) return fail(PW_ERR_ARG, "src and dst must not be NULL");
     if (narrays < 1 || narrays > 8) return fail(PW_ERR_ARG, "narrays=%d outside 1..8", narrays);
     if (unit != 4 && unit != 8 && unit != 16) return fail(PW_ERR_ARG, "unit=%d: need 4, 8 or 16", unit);
     if (bytes % (size_t)unit) return fail(PW_ERR_ARG, "bytes=%zu is not a multiple of the unit %d", bytes, unit);
     if (blocks < 0) return fail(PW_ERR_ARG, "blocks=%d: need 0 or more", blocks);
+    if (hints & ~(PW_COPY_NT_LOADS | PW_COPY_NT_STORES))
+        return fail(PW_ERR_ARG, "hints=%d: need an OR of PW_COPY_NT_LOADS and PW_COPY_NT_STORES", hints);
     // one pass: one thread per unit, and the grid's thread count must fit 32 bits
     if (blocks == 0 && bytes / (size_t)unit > 0xffffff00ULL)
         return fail(PW_ERR_SIZE, "one pass over %zu bytes in %d-byte units needs 2^32 threads or more", bytes, unit);
@@ -583,7 +585,7 @@ int pw_stream_copy(const void* const* src, void* const* dst, int narrays, size_t
     rc = check_device(all, 2 * narrays);
     if (rc) return rc;
     (void)hipGetLastError();
-    launch_stream_copy(src, dst, narrays, bytes, unit, blocks, (hipStream_t)stream);
+    launch_stream_copy(src, dst, narrays, bytes, unit, blocks, hints, (hipStream_t)stream);
     return launched("pw_stream_copy");
 }
 

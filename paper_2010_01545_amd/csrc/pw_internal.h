@@ -67,10 +67,11 @@ template <typename T> void launch_fill_uniform(T* st, const Geom& g, unsigned lo
                                                int field_id, double amp, int zero_lids,
                                                hipStream_t s);
 
-// Plain streaming copy of n arrays in units of 4, 8 or 16 bytes
-// (pw_copyref.hip), the bandwidth reference.
+// Plain streaming copy of n arrays in units of 4, 8 or 16 bytes, with
+// optional non-temporal loads/stores (pw_copyref.hip), the bandwidth
+// reference.
 void launch_stream_copy(const void* const* src, void* const* dst, int n, size_t bytes, int unit, int blocks,
-                        hipStream_t s);
+                        int hints, hipStream_t s);
 
 // Host-resident fields: chunked, pipelined forward (pw_offload.hip).  out_dev
 // holds the device addresses of su, sv, sw when they are mapped pinned host

@@ -25,6 +25,7 @@ KERNELS = {"auto": 0, "direct": 1, "march": 2}
 TUNE_KERNEL, TUNE_MARCH_VARIANT, TUNE_MARCH_LX, TUNE_COPY_OUT, TUNE_BLOCK_ORDER, TUNE_TALL_WAVES = 0, 1, 2, 3, 4, 5
 MARCH_VARIANTS = 8
 COPY_OUT = {"runtime": 0, "kernel": 1, "direct": 2, "auto": 3}
+COPY_NT_LOADS, COPY_NT_STORES = 1, 2     # pw_stream_copy hints
 ORDERS = {"default": -1, "xcd": 0, "natural": 1}   # or an int G: groups of G strips per XCD
 ERRORS = {-1: "PW_ERR_ARG", -2: "PW_ERR_ALIAS", -3: "PW_ERR_ALIGN", -4: "PW_ERR_SIZE",
           -5: "PW_ERR_UNSUPPORTED", -6: "PW_ERR_HIP"}
@@ -55,7 +56,7 @@ lib.pw_offload_workspace_bytes.restype = ctypes.c_size_t
 lib.pw_set_kernel.argtypes = [_i]
 lib.pw_set_tuning.argtypes = [_i, _i]
 lib.pw_get_tuning.argtypes = [_i, ctypes.POINTER(_i)]
-lib.pw_stream_copy.argtypes = [_vp, _vp, _i, ctypes.c_size_t, _i, _i, _vp]
+lib.pw_stream_copy.argtypes = [_vp, _vp, _i, ctypes.c_size_t, _i, _i, _i, _vp]
 lib.pw_last_error.restype = ctypes.c_char_p
 for _f in ("pw_advect_fwd", "pw_advect_adj", "pw_advect_fwd_adj", "pw_advect_fwd_host", "pw_advect_fwd_update",
            "pw_advect_fwd_host_static",
@@ -290,12 +291,13 @@ def alloc_fields(count, shape, dtype, device="cuda:0", align=4096):
     return [buf[off + q * step: off + q * step + n].view(shape) for q in range(count)]
 
 
-def stream_copy(src, dst, blocks=0, unit=4):
+def stream_copy(src, dst, blocks=0, unit=4, hints=0):
     """One launch of the library's plain streaming copy: dst[q] <- src[q] for
     lists of equally sized contiguous device tensors (the bandwidth reference
     of the advection kernels), in ``unit``-byte units (4, 8 or 16).
     ``blocks`` = 0: one unit per thread and array; > 0: that many workgroups
-    striding over the arrays."""
+    striding over the arrays.  ``hints``: 0 or an OR of COPY_NT_LOADS and
+    COPY_NT_STORES (non-temporal cache policy on the loads / stores)."""
     if len(src) != len(dst) or not 1 <= len(src) <= 8:
         raise ValueError("1..8 source and destination tensors")
     nbytes = src[0].numel() * src[0].element_size()
@@ -306,7 +308,7 @@ def stream_copy(src, dst, blocks=0, unit=4):
     sp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in src])
     dp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in dst])
     _check(lib.pw_stream_copy(ctypes.cast(sp, _vp), ctypes.cast(dp, _vp), n, nbytes, int(unit), int(blocks),
-                              _stream()))
+                              int(hints), _stream()))
 
 
 def get_tuning(knob):

@@ -255,15 +255,18 @@ def test_library_reads_no_environment():
 # ---------------------------------------------------------------- streaming copy reference
 def test_stream_copy_checks(lib):
     vp = ctypes.c_void_p
-    lib.pw_stream_copy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp]
+    lib.pw_stream_copy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   vp]
 
-    def call(src, dst, n, nbytes, blocks=0, unit=16):
+    def call(src, dst, n, nbytes, blocks=0, unit=16, hints=0):
         s = (vp * len(src))(*src)
         d = (vp * len(dst))(*dst)
-        return lib.pw_stream_copy(ctypes.cast(s, vp), ctypes.cast(d, vp), n, nbytes, unit, blocks, None)
+        return lib.pw_stream_copy(ctypes.cast(s, vp), ctypes.cast(d, vp), n, nbytes, unit, blocks, hints, None)
 
     src, dst = ADDR[:3], ADDR[3:6]
-    assert lib.pw_stream_copy(None, None, 3, 4096, 4, 0, None) == PW_ERR_ARG
+    assert lib.pw_stream_copy(None, None, 3, 4096, 4, 0, 0, None) == PW_ERR_ARG
+    assert call(src, dst, 3, 4096, hints=4) == PW_ERR_ARG               # unknown hint bit
+    assert call(src, dst, 3, 4096, hints=-1) == PW_ERR_ARG
     assert call(src, dst, 0, 4096) == PW_ERR_ARG
     assert call(ADDR[:9], ADDR[:9], 9, 4096) == PW_ERR_ARG
     assert call(src, dst, 3, 4100) == PW_ERR_ARG                       # not a multiple of 16

@@ -69,20 +69,22 @@ def test_pad_and_halo_match_oracle(pw, shape, halo):
     assert np.array_equal(st.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("hints", [0, 1, 2, 3])
 @pytest.mark.parametrize("unit,blocks", [(4, 0), (8, 0), (16, 0), (4, 7), (16, 3)])
 @pytest.mark.parametrize("n", [1, 3, 6, 8])
-def test_stream_copy_copies_exactly(pw, n, unit, blocks):
+def test_stream_copy_copies_exactly(pw, n, unit, blocks, hints):
     """The bandwidth reference copies every byte of every array, one pass or
-    striding, with a length that is not a multiple of a workgroup's units,
-    and writes nothing past the end of its destinations."""
-    log("stream copy n=%d unit=%d blocks=%d" % (n, unit, blocks))
+    striding, with either cache policy on loads and stores, with a length
+    that is not a multiple of a workgroup's units, and writes nothing past
+    the end of its destinations."""
+    log("stream copy n=%d unit=%d blocks=%d hints=%d" % (n, unit, blocks, hints))
     nbytes = 16 * 1000 + 48            # 1003 16-byte units, 4012 4-byte units
     g = torch.Generator().manual_seed(n * 100 + unit + blocks)
     src = [torch.randint(0, 255, (nbytes,), dtype=torch.uint8, generator=g).to(DEV) for _ in range(n)]
     pad = 256
     dst_full = [torch.full((nbytes + pad,), 0xA5, dtype=torch.uint8, device=DEV) for _ in range(n)]
     dst = [d[:nbytes] for d in dst_full]
-    pw.stream_copy(src, dst, blocks, unit)
+    pw.stream_copy(src, dst, blocks, unit, hints)
     torch.cuda.synchronize()
     for s, d in zip(src, dst_full):
         assert torch.equal(d[:nbytes], s)
