@@ -134,6 +134,33 @@ def test_offload_orders_on_callers_stream(pw, copy_out):
         assert np.array_equal(bb[h:-h, h:-h, h:-h], r[h:-h, h:-h, h:-h])
 
 
+def test_automatic_mode_tries_every_copy_out(pw):
+    """Twelve calls in the automatic copy-out mode on the same pinned arrays:
+    the first ones try each mode the outputs allow, later ones the fastest
+    (and every eighth the one sampled longest ago); every call gives the bits
+    of the runtime's copies."""
+    nx, ny, nz, seed, h = 11, 9, 64, 37, 2
+    fields, _, coef = host_case(nx, ny, nz, seed)
+    tzc1, tzc2, tcx, tcy = coef
+    st = [oracle.pad_periodic(f, h) for f in fields]
+    t1, t2 = torch.from_numpy(tzc1).to(DEV), torch.from_numpy(tzc2).to(DEV)
+    host_in = [torch.from_numpy(a).pin_memory() for a in st]
+    ws = torch.empty(pw.offload_workspace_bytes(host_in[0].shape, h, torch.float64, 3), dtype=torch.uint8,
+                     device=DEV)
+    ref = [torch.full(host_in[0].shape, float("nan"), dtype=torch.float64, pin_memory=True) for _ in range(3)]
+    with pw.tuning(copy_out="runtime"):
+        pw.fwd_host(*host_in, t1, t2, tcx, tcy, h, *ref, 3, ws)
+    torch.cuda.synchronize()
+    for call in range(12):
+        log("offload automatic call %d" % call)
+        outs = [torch.full(host_in[0].shape, float("nan"), dtype=torch.float64, pin_memory=True) for _ in range(3)]
+        with pw.tuning(copy_out="auto"):
+            pw.fwd_host(*host_in, t1, t2, tcx, tcy, h, *outs, 3, ws)
+        torch.cuda.synchronize()
+        for q in range(3):
+            assert np.array_equal(outs[q].numpy(), ref[q].numpy(), equal_nan=True), (call, q)
+
+
 def test_offload_argument_errors(pw):
     h = 2
     shape = (8 + 2 * h, 6 + 2 * h, 64 + 2 * h)
