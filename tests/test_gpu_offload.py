@@ -37,7 +37,8 @@ SHAPES = [((20, 13, 64, 2, 31), (1, 3, 7, 20)),
           ((9, 7, 7, 2, 32), (4, 9)),
           ((5, 7, 3, 2, 35), (2, 5)),
           ((9, 7, 3, 1, 36), (2, 4)),
-          ((6, 5, 3, 1, 34), (5,))]
+          ((6, 5, 3, 1, 34), (5,)),
+          ((7, 6, 150, 2, 38), (3, 7))]       # columns of 150 levels: the tall-column kernels
 MODES = ["pinned_runtime_copy", "pinned_copy_kernel", "pinned_direct", "pinned_auto", "pageable"]
 COPY_OUT = {"pinned_runtime_copy": "runtime", "pinned_copy_kernel": "kernel", "pinned_direct": "direct",
             "pinned_auto": "auto", "pageable": "auto"}

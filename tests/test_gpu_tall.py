@@ -120,6 +120,25 @@ def test_tall_wave_counts(pw, kind, nz, waves):
             assert _same(a, b), (path, q)
 
 
+@pytest.mark.parametrize("shape", [(5, 4, 1000, 1), (4, 5, 300, 32), (3, 4, 129, 32)],
+                         ids=lambda s: "x".join(map(str, s[:3])) + "h%d" % s[3])
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_tall_extremes(pw, kind, shape):
+    """A column of 1000 levels (four z-chunks of four wavefronts) with halo 1,
+    and the widest halo the x-marching kernels take (32, whose z-halo pads
+    fill a whole wavefront of lanes at each end of a column) at 300 and 129
+    levels: forward, adjoint and fused pass against the direct kernel."""
+    nx, ny, nz, h = shape
+    dtype, compute = KINDS[kind]
+    log("tall extreme %s %s" % (kind, shape))
+    fields, lams, coef = host_case(nx, ny, nz, 600 + nz + h, lam_seed=601 + nz + h)
+    for path in ("fwd", "adj", "fused"):
+        ref = _run(pw, fields, lams, coef, dtype, compute, h, path, "direct", {})
+        got = _run(pw, fields, lams, coef, dtype, compute, h, path, "march", {})
+        for q, (a, b) in enumerate(zip(ref, got)):
+            assert _same(a, b), (path, q)
+
+
 def test_tall_columns_match_oracle(pw):
     """FP64 forward and fused pass at 150 levels against the oracle: bitwise
     forward, adjoint within 1e-12 normwise; every interior column fully
