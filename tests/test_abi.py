@@ -279,3 +279,61 @@ def test_stream_copy_checks(lib):
     assert call(src, [dst[0], dst[0] + 4080, dst[2]], 3, 4096) == PW_ERR_ALIAS  # two destinations overlap
     assert call([0] + src[1:], dst, 3, 4096) == PW_ERR_ARG             # NULL entry
     assert call(src, dst, 3, (1 << 34) + (1 << 33), unit=4) == PW_ERR_SIZE   # 2^32 or more units in one pass
+
+
+# ---------------------------------------------------------------- C and C++ callers
+def _tool(name):
+    import shutil
+    path = shutil.which(name)
+    if not path:
+        pytest.fail("%s is needed to check the header" % name)
+    return path
+
+
+def test_header_is_strict_c99_and_cxx(tmp_path):
+    """The header compiles on its own as strict C99 and as C++17 (-pedantic
+    -Wall -Wextra -Werror)."""
+    import subprocess
+    body = '#include "pwadvect.h"\nint main(void) { return pw_version() > 0 ? 0 : 1; }\n'
+    for compiler, std, name in (("gcc", "-std=c99", "h.c"), ("g++", "-std=c++17", "h.cpp")):
+        src = tmp_path / name
+        src.write_text(body)
+        subprocess.run([_tool(compiler), std, "-pedantic", "-Wall", "-Wextra", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), "-fsyntax-only", str(src)], check=True)
+
+
+def test_every_declared_function_links_with_c_linkage(tmp_path):
+    """A C++ program that takes the address of every function the header
+    declares links against the library: each is defined, and with C linkage
+    (a declaration outside the header's extern "C" block would look for a
+    mangled name and fail to link)."""
+    import subprocess
+    names = declared_functions()
+    src = tmp_path / "all.cpp"
+    src.write_text('#include "pwadvect.h"\n#include <cstdio>\nint main() {\n  const void* fns[] = {\n' +
+                   "".join("    (const void*)&%s,\n" % n for n in names) +
+                   '  };\n  std::printf("%d\\n", (int)(sizeof fns / sizeof fns[0]));\n  return 0;\n}\n')
+    out = tmp_path / "all"
+    rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    subprocess.run([_tool("g++"), "-std=c++17", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(out), "-L", os.path.dirname(LIB), "-lpwadvect", "-Wl,-rpath," + os.path.dirname(LIB),
+                    "-Wl,-rpath-link," + rocm_lib],
+                   check=True)
+    ran = subprocess.run([str(out)], capture_output=True, text=True, check=True, timeout=60)
+    assert int(ran.stdout.strip()) == len(names)
+
+
+def test_c_caller_builds():
+    """The tests' plain-C caller (tests/c/pw_c_caller.c, run on the GPU by
+    test_gpu_c_caller) compiles as C99 against the header and links with the
+    library, the oracle and the HIP runtime, finding the in-tree library at
+    run time."""
+    import importlib.util
+    import subprocess
+    spec = importlib.util.spec_from_file_location("pw_c_caller_build", os.path.join(ROOT, "tests", "c", "build.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    exe = m.build_c_caller()
+    deps = subprocess.run(["ldd", exe], capture_output=True, text=True, check=True).stdout
+    line = [ln for ln in deps.splitlines() if "libpwadvect.so" in ln]
+    assert line and os.path.realpath(line[0].split("=>")[1].split("(")[0].strip()) == os.path.realpath(LIB)
