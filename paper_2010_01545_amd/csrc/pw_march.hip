@@ -634,6 +634,14 @@ Launch plan(const Geom& g, int TY, int lx, int slots, int order, int zw = 1)
             }
         }
     }
+    // at most 2^30 work items (a segment length asked for through the tuning
+    // knob may be short enough to exceed that only on grids of terabytes):
+    // longer segments otherwise
+    constexpr long long kMaxItems = 1LL << 30;
+    if (cols * (((long long)g.nx + lx - 1) / lx) > kMaxItems) {
+        const long long segs = kMaxItems / cols;     // cols < 2^26 for any grid check_shape admits
+        lx = (int)(((long long)g.nx + segs - 1) / segs);
+    }
     l.LX = lx;
     const int nseg = (g.nx + lx - 1) / lx;
     l.nblocks = (int)(cols * nseg);
