@@ -601,24 +601,29 @@ def main():
         log("bench: 1024^2 fwd f64 %.0f GB/s, f32 %.0f GB/s" % (precision["fwd_f64"]["alg_GBps"],
                                                              precision["fwd_f32"]["alg_GBps"]))
 
-    # columns of 128 levels (two wavefronts per column in the marching
-    # kernels), FP64 and FP32, 2048 x 2048 x 128: the same cells per plane
-    # as the headline grid's quarter, twice the levels
-    tall = None
-    if not args.no_paths:
-        tnx, tny, tnz, tseed = 2048, 2048, 128, 5
+    # taller columns, FP64 and FP32: 128 levels at 2048 x 2048 (two
+    # wavefronts per column in the marching kernels; the same cells per plane
+    # as the headline grid's quarter, twice the levels) and 400 levels at
+    # 2048 x 1024 (two z-chunks of 254 levels, four wavefronts each)
+    def tall_record(tnx, tny, tnz, tseed):
         ct = tnx * tny * tnz
-        tall = {"workload": "tall columns %dx%dx%d, 10 launches each" % (tnx, tny, tnz)}
+        rec = {"workload": "tall columns %dx%dx%d, 10 launches each" % (tnx, tny, tnz)}
         for tag, dt, esz in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
             g = Grid(pw, torch, tnx, tny, tnz, h, dt, tseed, True)
             settle(torch, lambda: g.launch(pw, "fused"))
             for p in ("fwd", "adj", "fused"):
                 g.launch(pw, p)
-                tall[p + "_" + tag] = path_record(p, esz, ct, time_launches(torch, lambda: g.launch(pw, p), 10))
+                rec[p + "_" + tag] = path_record(p, esz, ct, time_launches(torch, lambda: g.launch(pw, p), 10))
             del g
             torch.cuda.empty_cache()
-        log("bench: 2048^2 x 128 fwd f64 %.2f ms (%.0f GB/s), fused f64 %.2f ms" % (
-            tall["fwd_f64"]["ms_avg"], tall["fwd_f64"]["alg_GBps"], tall["fused_f64"]["ms_avg"]))
+        log("bench: %dx%dx%d fwd f64 %.2f ms (%.0f GB/s), fused f64 %.2f ms" % (
+            tnx, tny, tnz, rec["fwd_f64"]["ms_avg"], rec["fwd_f64"]["alg_GBps"], rec["fused_f64"]["ms_avg"]))
+        return rec
+
+    tall = tall_chunked = None
+    if not args.no_paths:
+        tall = tall_record(2048, 2048, 128, 5)
+        tall_chunked = tall_record(2048, 1024, 400, 6)
 
     kname = "fused_f64"
     traffic = measured_traffic(kname, args.workload)
@@ -645,6 +650,7 @@ def main():
         "separate_allocations": separate,
         "precision_workload": precision,
         "tall_columns": tall,
+        "tall_columns_chunked": tall_chunked,
         "medium_cache_resident": medium,
         "source_hash": kernel_source_hash(),
         "clock_settle_s": CLOCK_SETTLE_S,
