@@ -363,11 +363,12 @@ def offload_measure(pw, torch, reps=4, chunk=64):
         return ev[0].elapsed_time(ev[1]) / n
 
     run = lambda: pw.fwd_host(*host_in, g.t1, g.t2, g.tcx, g.tcy, h, *host_out, chunk, ws)
-    # copy-out modes: the runtime's copies, the library's copy kernel, direct
-    # writes by the advection kernel, and the automatic choice among them (the
-    # default; it learns from every call's time); all warmed, then timed call
-    # by call in alternation so that none profits from another's warm-up
-    calls = {"runtime": [], "kernel": [], "direct": [], "auto": []}
+    # copy-out modes: the runtime's copies, the library's copy kernel and
+    # direct writes by the advection kernel, warmed, then timed call by call
+    # in alternation so that none profits from another's warm-up; then the
+    # automatic choice among them (the default; it learns from every call's
+    # time)
+    calls = {"runtime": [], "kernel": [], "direct": []}
     for _ in range(2):      # (the first call of each mode carries one-time costs)
         for mode in calls:
             with pw.tuning(copy_out=mode):
@@ -377,6 +378,12 @@ def offload_measure(pw, torch, reps=4, chunk=64):
         for mode in calls:
             with pw.tuning(copy_out=mode):
                 calls[mode].append(timed(run, 1))
+    # the automatic mode as a caller uses it: consecutive calls, after the
+    # calls above taught it each mode's time on this device
+    calls["auto"] = []
+    with pw.tuning(copy_out="auto"):
+        for _ in range(2 * reps):
+            calls["auto"].append(timed(run, 1))
     med = lambda v: sorted(v)[len(v) // 2]
     by_mode = {m: med(v) for m, v in calls.items()}
     default_mode = {v: k for k, v in pw.COPY_OUT.items()}[pw.get_tuning(pw.TUNE_COPY_OUT)]

@@ -37,8 +37,11 @@
 // copy kernel).  In the automatic mode (the default) every call is timed
 // with two events on the caller's stream; a later call reads the times of
 // the calls that have finished (hipEventQuery: it never waits) and takes the
-// mode with the lowest recent time per byte, after first trying each mode
-// the call allows and trying the others again every eighth call.
+// mode with the lowest mean time per byte over its last three calls, after
+// first trying each mode the call allows and trying the others again every
+// eighth call.  The mean, not the median: where the runtime's copies are
+// slow in most calls and fast in a few, the median of three may still see
+// the fast ones while the copy kernel would be faster on average.
 #include <algorithm>
 #include <mutex>
 
@@ -101,7 +104,7 @@ void copy_rows(const void* src, void* dst, size_t pitch, size_t row, int rows, h
 constexpr int kModes = 3;       // PW_COPY_OUT_RUNTIME, _KERNEL, _DIRECT
 constexpr int kTimed = 8;       // calls whose times may be outstanding
 constexpr int kRetryEvery = 8;  // automatic mode: retry the other modes every this many calls
-constexpr int kSamples = 3;     // times kept per mode (one slow call among three does not move the choice)
+constexpr int kSamples = 3;     // times kept per mode; its cost is their mean
 
 struct CallTimer {
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -116,8 +119,9 @@ struct DeviceQueues {
     hipEvent_t start = nullptr, done_in[kBuffers] = {}, done_kernel[kBuffers] = {}, done_out[kBuffers] = {},
                end_out = nullptr;
     // automatic copy-out choice: the last kSamples times of each mode in ms
-    // per GB, their cost (the median of three, the lower of two; < 0: no
-    // sample yet), the call count at its last sample, and the timers in flight
+    // per GB, their cost (their mean, the expected time of a mode whose calls
+    // are now fast, now slow; < 0: no sample yet), the call count at its last
+    // sample, and the timers in flight
     double samples[kModes][kSamples] = {};
     int nsamples[kModes] = {0, 0, 0};
     double cost[kModes] = {-1.0, -1.0, -1.0};
@@ -178,8 +182,9 @@ void harvest_timers(DeviceQueues* q)
             s[0] = (double)ms / t.gbytes;
             if (q->nsamples[m] < kSamples) ++q->nsamples[m];
             const int n = q->nsamples[m];
-            const double lo = std::min(s[0], s[1]), hi = std::max(s[0], s[1]);
-            q->cost[m] = n == 1 ? s[0] : n == 2 ? lo : std::max(lo, std::min(hi, s[2]));
+            double sum = 0.0;
+            for (int i = 0; i < n; ++i) sum += s[i];
+            q->cost[m] = sum / n;
             q->sampled_at[m] = q->calls;
         }
         (void)hipGetLastError();
