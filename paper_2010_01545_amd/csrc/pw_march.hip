@@ -865,9 +865,10 @@ void dispatch(const MarchArgs<T, NF>& m, const Geom& g, MarchTune t, hipStream_t
             for (int z = 2; z <= 4; ++z)
                 if (lanes[z] * 10 <= fewest * 11) zw = z;
         }
-        // natural order for the two-wavefront forward (3-11% faster at 100,
-        // 128, 300 and 400 levels), XCD ranges for the rest (natural is up to
-        // 8% slower for the six-field kernels at 200 and 256 levels)
+        // natural order for the two-wavefront forward (3-7% faster at 100 and
+        // 128 levels, 3-13% in chunks of 126 levels at 300, 400 and 600),
+        // XCD ranges for the rest (natural is up to 8% slower for the
+        // six-field kernels at 200 and 256 levels)
         const int order = t.order >= 0 ? t.order : (NF == 3 && zw == 2) ? 1 : 0;
         if (zw == 2)
             go_tall<T, C, NF, WS, WG, UPD, 2>(m, g, t.lx, order, s);
