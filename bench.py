@@ -522,22 +522,6 @@ def main():
     del g
     torch.cuda.empty_cache()
 
-    # the same FP64 launches over twelve separately allocated arrays: their
-    # speed depends on where each allocation lands in HBM
-    separate = None
-    if not args.no_paths and not args.no_separate:
-        g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True, pooled=False)
-        separate = {"layout": "one allocation per array"}
-        settle(torch, lambda: g.launch(pw, "fused"))
-        for p in ("fused", "fwd"):
-            g.launch(pw, p)
-            separate[p + "_f64"] = path_record(p, 8, cells, time_launches(torch, lambda: g.launch(pw, p),
-                                                                          args.paths_reps))
-            separate[p + "_f64"]["time_vs_pooled"] = separate[p + "_f64"]["ms_avg"] / paths[p + "_f64"]["ms_avg"]
-        log("bench: separately allocated arrays: fused f64 %.2f ms, fwd f64 %.2f ms" % (
-            separate["fused_f64"]["ms_avg"], separate["fwd_f64"]["ms_avg"]))
-        del g
-        torch.cuda.empty_cache()
     if not args.no_paths:
         g = Grid(pw, torch, nx, ny, nz, h, torch.float32, seed, True)
         settle(torch, lambda: g.launch(pw, "fused"))
@@ -572,6 +556,25 @@ def main():
         for p in ("fwd", "adj", "fused"):
             for v in ("_f32", "_f32f64", "_f16", "_bf16"):
                 paths[p + v]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + v]["ms_avg"]
+
+    # the same FP64 launches over twelve separately allocated arrays: their
+    # speed depends on where each allocation lands in HBM (measured after the
+    # other storage types: the grids allocated after these twelve arrays were
+    # freed ran slower, FP32 fused 10.65 ms against 9.42 without them)
+    separate = None
+    if not args.no_paths and not args.no_separate:
+        g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True, pooled=False)
+        separate = {"layout": "one allocation per array"}
+        settle(torch, lambda: g.launch(pw, "fused"))
+        for p in ("fused", "fwd"):
+            g.launch(pw, p)
+            separate[p + "_f64"] = path_record(p, 8, cells, time_launches(torch, lambda: g.launch(pw, p),
+                                                                          args.paths_reps))
+            separate[p + "_f64"]["time_vs_pooled"] = separate[p + "_f64"]["ms_avg"] / paths[p + "_f64"]["ms_avg"]
+        log("bench: separately allocated arrays: fused f64 %.2f ms, fwd f64 %.2f ms" % (
+            separate["fused_f64"]["ms_avg"], separate["fwd_f64"]["ms_avg"]))
+        del g
+        torch.cuda.empty_cache()
 
     # 256x256x64 (the medium workload): the forward's six FP64 arrays (221 MB)
     # fit the 256 MB Infinity Cache, so its rate is not an HBM figure

@@ -37,11 +37,14 @@
 // copy kernel).  In the automatic mode (the default) every call is timed
 // with two events on the caller's stream; a later call reads the times of
 // the calls that have finished (hipEventQuery: it never waits) and takes the
-// mode with the lowest mean time per byte over its last three calls, after
+// mode with the lowest mean time per byte over its last eight calls, after
 // first trying each mode the call allows and trying the others again every
-// eighth call.  The mean, not the median: where the runtime's copies are
-// slow in most calls and fast in a few, the median of three may still see
-// the fast ones while the copy kernel would be faster on average.
+// eighth call.  The mean of eight estimates the expected time of a mode
+// whose calls are now fast, now slow: a median of three stayed on the
+// runtime's copies where they were slow in most calls (457 ms against 271 ms
+// for the copy kernel), a mean of three left them for many calls after one
+// slow call among fast ones (210 ms in most calls, 457 ms in about one of
+// five: 259 ms on average, still below the copy kernel).
 #include <algorithm>
 #include <mutex>
 
@@ -104,7 +107,7 @@ void copy_rows(const void* src, void* dst, size_t pitch, size_t row, int rows, h
 constexpr int kModes = 3;       // PW_COPY_OUT_RUNTIME, _KERNEL, _DIRECT
 constexpr int kTimed = 8;       // calls whose times may be outstanding
 constexpr int kRetryEvery = 8;  // automatic mode: retry the other modes every this many calls
-constexpr int kSamples = 3;     // times kept per mode; its cost is their mean
+constexpr int kSamples = 8;     // times kept per mode; its cost is their mean
 
 struct CallTimer {
     hipEvent_t t0 = nullptr, t1 = nullptr;
