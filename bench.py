@@ -558,9 +558,7 @@ def main():
                 paths[p + v]["speedup_vs_f64"] = paths[p + "_f64"]["ms_avg"] / paths[p + v]["ms_avg"]
 
     # the same FP64 launches over twelve separately allocated arrays: their
-    # speed depends on where each allocation lands in HBM (measured after the
-    # other storage types: the grids allocated after these twelve arrays were
-    # freed ran slower, FP32 fused 10.65 ms against 9.42 without them)
+    # speed depends on where each allocation lands in HBM
     separate = None
     if not args.no_paths and not args.no_separate:
         g = Grid(pw, torch, nx, ny, nz, h, torch.float64, seed, True, pooled=False)
