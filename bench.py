@@ -438,8 +438,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the PW advection path is measured on one "
-              "GPU's grid; a multi-GPU run (x-slab decomposition with halo exchange) is not "
-              "part of this build.", file=sys.stderr)
+              "GPU's grid; the library has no multi-GPU path (x-slab decomposition with halo "
+              "exchange).", file=sys.stderr)
         sys.exit(2)
 
     import torch
