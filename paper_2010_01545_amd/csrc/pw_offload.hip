@@ -37,14 +37,15 @@
 // copy kernel).  In the automatic mode (the default) every call is timed
 // with two events on the caller's stream; a later call reads the times of
 // the calls that have finished (hipEventQuery: it never waits) and takes the
-// mode with the lowest mean time per byte over its last eight calls, after
-// first trying each mode the call allows and trying the others again every
-// eighth call.  The mean of eight estimates the expected time of a mode
-// whose calls are now fast, now slow: a median of three stayed on the
-// runtime's copies where they were slow in most calls (457 ms against 271 ms
-// for the copy kernel), a mean of three left them for many calls after one
-// slow call among fast ones (210 ms in most calls, 457 ms in about one of
-// five: 259 ms on average, still below the copy kernel).
+// mode with the lowest mean time per byte over its last eight calls, the
+// slowest of them left out, after first trying each mode the call allows
+// and trying the others again every eighth call.  That estimates the
+// expected time of a mode whose calls are now fast, now slow: a median of
+// three stayed on the runtime's copies where they were slow in most calls
+// (457 ms against 271 ms for the copy kernel); a plain mean left them for
+// several calls after one or two slow calls among fast ones (210 ms in most
+// calls, 457 ms in one or two of eight, still below the copy kernel on
+// average).
 #include <algorithm>
 #include <mutex>
 
@@ -107,7 +108,7 @@ void copy_rows(const void* src, void* dst, size_t pitch, size_t row, int rows, h
 constexpr int kModes = 3;       // PW_COPY_OUT_RUNTIME, _KERNEL, _DIRECT
 constexpr int kTimed = 8;       // calls whose times may be outstanding
 constexpr int kRetryEvery = 8;  // automatic mode: retry the other modes every this many calls
-constexpr int kSamples = 8;     // times kept per mode; its cost is their mean
+constexpr int kSamples = 8;     // times kept per mode; its cost is their mean without the slowest
 
 struct CallTimer {
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -122,9 +123,9 @@ struct DeviceQueues {
     hipEvent_t start = nullptr, done_in[kBuffers] = {}, done_kernel[kBuffers] = {}, done_out[kBuffers] = {},
                end_out = nullptr;
     // automatic copy-out choice: the last kSamples times of each mode in ms
-    // per GB, their cost (their mean, the expected time of a mode whose calls
-    // are now fast, now slow; < 0: no sample yet), the call count at its last
-    // sample, and the timers in flight
+    // per GB, their cost (their mean without the slowest, the expected time of
+    // a mode whose calls are now fast, now slow; < 0: no sample yet), the call
+    // count at its last sample, and the timers in flight
     double samples[kModes][kSamples] = {};
     int nsamples[kModes] = {0, 0, 0};
     double cost[kModes] = {-1.0, -1.0, -1.0};
@@ -185,9 +186,13 @@ void harvest_timers(DeviceQueues* q)
             s[0] = (double)ms / t.gbytes;
             if (q->nsamples[m] < kSamples) ++q->nsamples[m];
             const int n = q->nsamples[m];
-            double sum = 0.0;
-            for (int i = 0; i < n; ++i) sum += s[i];
-            q->cost[m] = sum / n;
+            double sum = 0.0, worst = 0.0;
+            for (int i = 0; i < n; ++i) {
+                sum += s[i];
+                worst = std::max(worst, s[i]);
+            }
+            // from four samples on, the slowest is left out
+            q->cost[m] = n >= 4 ? (sum - worst) / (n - 1) : sum / n;
             q->sampled_at[m] = q->calls;
         }
         (void)hipGetLastError();
